@@ -1,0 +1,217 @@
+"""MI355X-native AES counter mode behind a C ABI (libaesctr.so).
+
+Thin Python binding with the library's own names.  Buffers are torch CUDA
+tensors (any dtype, contiguous) or raw device addresses; streams are
+``torch.cuda.Stream`` objects or raw ``hipStream_t`` integers (default: torch's
+current stream).  Torch only supplies memory and streams; the cipher runs in
+the library's HIP kernels.  There is no CPU path: if the library is missing,
+importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _native as N
+from ._native import (AES_VARIANT_AUTO, AES_VARIANT_BITSLICE, AES_VARIANT_TTABLE,  # noqa: F401
+                      aes_batch_cfg_t, aes_ctr_desc_t, aes_engine_cfg_t, aes_launch_cfg_t,
+                      aes_sched_t, aes_stats_t)
+
+lib = N.lib
+
+
+class AesError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        msg = lib.aes_strerror(status).decode()
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise AesError(rc, where)
+    return rc
+
+
+def aes_strerror(status: int) -> str:
+    return lib.aes_strerror(status).decode()
+
+
+def aes_expand_key(key: bytes) -> aes_sched_t:
+    """FIPS-197 KeyExpansion of a 16- or 32-byte key (host only)."""
+    s = aes_sched_t()
+    _check(lib.aes_expand_key(bytes(key), 8 * len(key), ctypes.byref(s)), "aes_expand_key")
+    return s
+
+
+def _is_tensor(x) -> bool:
+    return hasattr(x, "data_ptr") and hasattr(x, "element_size")
+
+
+def _addr(x) -> int | None:
+    if x is None:
+        return None
+    if _is_tensor(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    return int(x)
+
+
+def _nbytes(x) -> int:
+    return x.numel() * x.element_size()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _nonce(nonce: bytes) -> bytes:
+    nonce = bytes(nonce)
+    if len(nonce) != 12:
+        raise ValueError("nonce must be 12 bytes")
+    return nonce
+
+
+def launch_cfg(variant: int = 0, blocks_per_lane: int = 0, wg_size: int = 0, grid: int = 0,
+               lds_copies: int = 0) -> aes_launch_cfg_t:
+    c = aes_launch_cfg_t()
+    c.variant, c.blocks_per_lane, c.wg_size, c.grid, c.lds_copies = (
+        variant, blocks_per_lane, wg_size, grid, lds_copies)
+    return c
+
+
+def aes_ctr_crypt(sched: aes_sched_t, nonce: bytes, ctr0: int, x, out=None, length: int | None = None,
+                  stream=None, cfg: aes_launch_cfg_t | None = None):
+    """out = x XOR AES-CTR keystream; returns ``out`` (a new tensor if None).
+
+    ``x``/``out`` are device tensors or raw device addresses (then give
+    ``length``).  Asynchronous on ``stream``."""
+    if out is None:
+        if not _is_tensor(x):
+            raise ValueError("out is required when x is a raw address")
+        import torch
+        out = torch.empty_like(x)
+    n = length if length is not None else _nbytes(x)
+    st = _stream(stream)
+    if cfg is None:
+        rc = lib.aes_ctr_crypt(ctypes.byref(sched), _nonce(nonce), ctr0 & 0xFFFFFFFF,
+                               _addr(x), _addr(out), n, st)
+    else:
+        rc = lib.aes_ctr_crypt_cfg(ctypes.byref(sched), _nonce(nonce), ctr0 & 0xFFFFFFFF,
+                                   _addr(x), _addr(out), n, ctypes.byref(cfg), st)
+    _check(rc, "aes_ctr_crypt")
+    return out
+
+
+class Request:
+    """One batch/engine request: key schedule, nonce, start counter, buffers."""
+
+    def __init__(self, sched: aes_sched_t, nonce: bytes, ctr0: int, x, out, length: int | None = None):
+        self.sched, self.nonce, self.ctr0 = sched, _nonce(nonce), ctr0 & 0xFFFFFFFF
+        self.x, self.out = x, out
+        self.length = length if length is not None else _nbytes(x)
+
+    def desc(self) -> aes_ctr_desc_t:
+        d = aes_ctr_desc_t()
+        d.in_ = _addr(self.x)
+        d.out = _addr(self.out)
+        d.len = self.length
+        d.sched = ctypes.pointer(self.sched)
+        d.nonce[:] = list(self.nonce)
+        d.ctr0 = self.ctr0
+        return d
+
+
+def make_desc_array(reqs) -> ctypes.Array:
+    arr = (aes_ctr_desc_t * max(len(reqs), 1))()
+    for i, r in enumerate(reqs):
+        arr[i] = r.desc()
+    return arr
+
+
+def aes_ctr_crypt_batch(reqs, stream=None, cfg: aes_batch_cfg_t | None = None, descs=None) -> None:
+    """Encrypt every request with one persistent launch (asynchronous).
+
+    ``descs`` may carry a prebuilt descriptor array (from make_desc_array) to
+    keep Python marshalling out of a timed loop."""
+    arr = descs if descs is not None else make_desc_array(reqs)
+    n = len(reqs)
+    st = _stream(stream)
+    if cfg is None:
+        rc = lib.aes_ctr_crypt_batch(arr, n, st)
+    else:
+        rc = lib.aes_ctr_crypt_batch_cfg(arr, n, ctypes.byref(cfg), st)
+    _check(rc, "aes_ctr_crypt_batch")
+
+
+def batch_cfg(tile_bytes: int = 0, wg_size: int = 0, grid: int = 0, blocks_per_lane: int = 0,
+              use_graph: int = 1) -> aes_batch_cfg_t:
+    c = aes_batch_cfg_t()
+    c.tile_bytes, c.wg_size, c.grid, c.blocks_per_lane, c.use_graph = (
+        tile_bytes, wg_size, grid, blocks_per_lane, use_graph)
+    return c
+
+
+class Engine:
+    """submit -> poll/wait executor (aes_engine_*)."""
+
+    def __init__(self, budget_bytes: int = 0, n_streams: int = 0, max_batch_reqs: int = 0,
+                 max_batch_bytes: int = 0, key_slots: int = 0, host_buffers: bool = False,
+                 device: int = -1):
+        c = aes_engine_cfg_t()
+        c.budget_bytes, c.n_streams, c.max_batch_reqs = budget_bytes, n_streams, max_batch_reqs
+        c.max_batch_bytes, c.key_slots, c.host_buffers, c.device = (
+            max_batch_bytes, key_slots, int(host_buffers), device)
+        h = ctypes.c_void_p()
+        _check(lib.aes_engine_create(ctypes.byref(c), ctypes.byref(h)), "aes_engine_create")
+        self._h = h
+
+    def submit(self, req: Request) -> int:
+        d = req.desc()
+        t = ctypes.c_uint64()
+        _check(lib.aes_submit(self._h, ctypes.byref(d), ctypes.byref(t)), "aes_submit")
+        return t.value
+
+    def submit_desc(self, d: aes_ctr_desc_t) -> int:
+        t = ctypes.c_uint64()
+        _check(lib.aes_submit(self._h, ctypes.byref(d), ctypes.byref(t)), "aes_submit")
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        return _check(lib.aes_poll(self._h, ticket), "aes_poll") == 1
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> None:
+        _check(lib.aes_wait(self._h, ticket, timeout_us), "aes_wait")
+
+    def stats(self) -> dict:
+        s = aes_stats_t()
+        _check(lib.aes_engine_stats(self._h, ctypes.byref(s)), "aes_engine_stats")
+        return {name: getattr(s, name) for name, _ in aes_stats_t._fields_}
+
+    def reset_stats(self) -> None:
+        _check(lib.aes_engine_reset_stats(self._h), "aes_engine_reset_stats")
+
+    def completion_fd(self) -> int:
+        return _check(lib.aes_engine_completion_fd(self._h), "aes_engine_completion_fd")
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib.aes_engine_destroy(self._h), "aes_engine_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,198 @@
+// api.cpp -- C ABI entry points for single buffers: validation, launch-shape
+// resolution and dispatch to the keystream kernels.
+#include <mutex>
+#include <string.h>
+
+#include "aesctr_internal.h"
+#include "tune.h"
+
+namespace aesctr {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mu;
+DeviceInfo g_dev[kMaxDevices];
+bool g_dev_ok[kMaxDevices];
+
+}  // namespace
+
+int device_info(DeviceInfo *out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return AES_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_dev_ok[dev]) {
+        DeviceInfo d{};
+        d.ordinal = dev;
+        if (hipDeviceGetAttribute(&d.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&d.max_lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess) {
+            (void)hipGetLastError();
+            return AES_EDEVICE;
+        }
+        g_dev[dev] = d;
+        g_dev_ok[dev] = true;
+    }
+    *out = g_dev[dev];
+    return AES_OK;
+}
+
+int check_sched(const aes_sched_t *s)
+{
+    if (!s)
+        return AES_EINVAL;
+    if (!((s->key_bits == 128 && s->nr == 10) || (s->key_bits == 256 && s->nr == 14)))
+        return AES_EINVAL;
+    return AES_OK;
+}
+
+// Argument checks shared by every entry point that takes a buffer pair.
+int check_buffers(const void *in, const void *out, uint64_t len)
+{
+    if (len == 0)
+        return AES_OK;
+    if (!in || !out)
+        return AES_EINVAL;
+    if (len > (static_cast<uint64_t>(1) << 36))
+        return AES_ERANGE;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in);
+    const uintptr_t b = reinterpret_cast<uintptr_t>(out);
+    if (a > UINTPTR_MAX - len || b > UINTPTR_MAX - len)
+        return AES_EINVAL;
+    if (a != b && a < b + len && b < a + len)
+        return AES_EOVERLAP;
+    return AES_OK;
+}
+
+Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &di)
+{
+    Shape sh{};
+    sh.variant = variant == AES_VARIANT_AUTO ? AES_VARIANT_TTABLE : variant;
+    TuneEntry te;
+    if (tune_lookup(sh.variant, key_bits, len, &te)) {
+        sh.bpl = te.bpl;
+        sh.wg = te.wg;
+        sh.copies = te.copies;
+        sh.grid = te.grid_per_cu * di.num_cus;
+    } else if (sh.variant == AES_VARIANT_TTABLE) {
+        // Measured on MI355X: small messages prefer smaller workgroups with
+        // one block per lane; mid sizes two blocks per lane and the 64-copy
+        // table; large ones the 32-copy table.
+        sh.grid = di.num_cus;
+        if (len <= (2u << 20)) {
+            sh.bpl = 1; sh.wg = 512; sh.copies = 32;
+        } else if (len <= (64u << 20)) {
+            sh.bpl = 2; sh.wg = 1024; sh.copies = 64;
+        } else {
+            sh.bpl = key_bits == 128 ? 2 : 1; sh.wg = 1024; sh.copies = 32;
+        }
+    } else {
+        sh.bpl = 1;
+        sh.wg = 256;
+        sh.copies = 0;
+        sh.grid = 2 * di.num_cus;
+    }
+    return sh;
+}
+
+// Never launch more workgroups than there is work for.
+static void clamp_grid(Shape *sh, uint64_t len)
+{
+    uint64_t blocks = (len + 15) / 16;
+    uint64_t per_wg;
+    if (sh->variant == AES_VARIANT_BITSLICE)
+        per_wg = static_cast<uint64_t>(sh->wg) * 8;    // 512 blocks per wave
+    else
+        per_wg = static_cast<uint64_t>(sh->wg) * sh->bpl;
+    uint64_t need = (blocks + per_wg - 1) / per_wg;
+    if (need < 1)
+        need = 1;
+    if (static_cast<uint64_t>(sh->grid) > need)
+        sh->grid = static_cast<int>(need);
+}
+
+}  // namespace aesctr
+
+using namespace aesctr;
+
+extern "C" const char *aes_strerror(int status)
+{
+    switch (status) {
+    case AES_OK: return "AES_OK: success";
+    case AES_EINVAL: return "AES_EINVAL: invalid argument";
+    case AES_ENOMEM: return "AES_ENOMEM: out of memory";
+    case AES_EAGAIN: return "AES_EAGAIN: over the engine memory budget";
+    case AES_ERANGE: return "AES_ERANGE: message longer than 2^32 blocks";
+    case AES_EDEVICE: return "AES_EDEVICE: HIP device error or no device";
+    case AES_ENOTFOUND: return "AES_ENOTFOUND: unknown ticket";
+    case AES_ETIMEDOUT: return "AES_ETIMEDOUT: timed out";
+    case AES_EOVERLAP: return "AES_EOVERLAP: input and output partially overlap";
+    case AES_ECLOSED: return "AES_ECLOSED: engine is shutting down";
+    case AES_ECANCELED: return "AES_ECANCELED: request canceled";
+    default: return "unknown aes status";
+    }
+}
+
+extern "C" int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[12], uint32_t ctr0,
+                                 const void *in, void *out, size_t len, const aes_launch_cfg_t *cfg,
+                                 void *stream)
+{
+    int rc = check_sched(sched);
+    if (rc != AES_OK)
+        return rc;
+    if (!nonce)
+        return AES_EINVAL;
+    if ((rc = check_buffers(in, out, len)) != AES_OK)
+        return rc;
+    int variant = cfg ? cfg->variant : AES_VARIANT_AUTO;
+    if (variant < AES_VARIANT_AUTO || variant > AES_VARIANT_BITSLICE)
+        return AES_EINVAL;
+    if (cfg) {
+        if (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2 &&
+            cfg->blocks_per_lane != 4)
+            return AES_EINVAL;
+        if (cfg->wg_size != 0 && (cfg->wg_size < 64 || cfg->wg_size > 1024 || cfg->wg_size % 64 != 0))
+            return AES_EINVAL;
+        if (cfg->grid < 0 || (cfg->lds_copies != 0 && cfg->lds_copies != 32 && cfg->lds_copies != 64))
+            return AES_EINVAL;
+    }
+    if (len == 0)
+        return AES_OK;
+
+    DeviceInfo di;
+    if ((rc = device_info(&di)) != AES_OK)
+        return rc;
+    Shape sh = default_shape(variant, sched->key_bits, len, di);
+    if (cfg) {
+        if (cfg->blocks_per_lane) sh.bpl = cfg->blocks_per_lane;
+        if (cfg->wg_size) sh.wg = cfg->wg_size;
+        if (cfg->grid) sh.grid = cfg->grid;
+        if (cfg->lds_copies) sh.copies = cfg->lds_copies;
+    }
+    clamp_grid(&sh, len);
+
+    KeyMaterial km;
+    make_key_material(*sched, nonce, &km);
+    CtrArgs a{};
+    a.in = static_cast<const uint8_t *>(in);
+    a.out = static_cast<uint8_t *>(out);
+    a.len = len;
+    a.ctr0 = ctr0;
+    a.x0 = km.x0;
+    memcpy(a.k1, km.k1, sizeof(a.k1));
+    memcpy(a.rk, km.rk, sizeof(a.rk));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (sh.variant == AES_VARIANT_BITSLICE)
+        return launch_ctr_bitslice(a, km.nr, sh, st);
+    return launch_ctr_ttable(a, km.nr, sh, st);
+}
+
+extern "C" int aes_ctr_crypt(const aes_sched_t *sched, const uint8_t nonce[12], uint32_t ctr0,
+                             const void *in, void *out, size_t len, void *stream)
+{
+    return aes_ctr_crypt_cfg(sched, nonce, ctr0, in, out, len, nullptr, stream);
+}

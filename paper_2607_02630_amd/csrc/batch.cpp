@@ -1,0 +1,276 @@
+// batch.cpp -- aes_ctr_crypt_batch: descriptor table staging and the
+// captured-graph launch.
+//
+// Per (device, stream) the library keeps a context: a device table (header +
+// up to kMaxBatch descriptors) and a ring of pinned host staging slots, each
+// with an executable HIP graph of two nodes -- the host-to-device copy of that
+// slot into the table, then the persistent batch kernel.  A call fills a free
+// slot, sets its graph's copy size, and launches the graph on the caller's
+// stream; nothing is re-captured between calls.  A slot (and its graph) is
+// reused only after the event recorded behind its last launch completes, so
+// no update touches a graph still in flight.  The tile counter the kernel
+// claims work from is part of every upload (0), so no memset node is needed.
+// The call cannot itself be captured into a caller's graph (its staging would
+// be rewritten by later calls): on a capturing stream it returns AES_EINVAL.
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string.h>
+#include <vector>
+
+#include "aesctr_internal.h"
+#include "tune.h"
+
+namespace aesctr {
+
+namespace {
+
+constexpr int kSlots = 4;
+constexpr size_t kTableBytes = sizeof(BatchHeader) + sizeof(BatchDesc) * kMaxBatch;
+
+struct BatchShape {
+    int tile_bytes, wg, grid, bpl, use_graph;
+};
+
+struct SlotGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy_node = nullptr;
+    int grid = 0, bpl = 0;
+};
+
+struct BatchCtx {
+    std::mutex mu;
+    int device = -1;
+    void *dev_table = nullptr;
+    uint8_t *staging[kSlots] = {};
+    hipEvent_t done[kSlots] = {};
+    bool used[kSlots] = {};
+    SlotGraph g[kSlots];
+    int next_slot = 0;
+};
+
+std::mutex g_ctx_mu;
+// Contexts live until process exit (freeing them from a static destructor
+// could run after the HIP runtime has shut down).
+std::map<std::pair<int, void *>, BatchCtx *> g_ctx;
+
+int init_ctx(BatchCtx *c, int device)
+{
+    c->device = device;
+    if (hipMalloc(&c->dev_table, kTableBytes) != hipSuccess)
+        return AES_ENOMEM;
+    for (int i = 0; i < kSlots; ++i) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->staging[i]), kTableBytes, hipHostMallocDefault) !=
+            hipSuccess)
+            return AES_ENOMEM;
+        if (hipEventCreateWithFlags(&c->done[i], hipEventDisableTiming) != hipSuccess)
+            return AES_EDEVICE;
+    }
+    return AES_OK;
+}
+
+BatchCtx *get_ctx(int device, void *stream, int *rc)
+{
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    auto key = std::make_pair(device, stream);
+    auto it = g_ctx.find(key);
+    if (it != g_ctx.end()) {
+        *rc = AES_OK;
+        return it->second;
+    }
+    BatchCtx *c = new BatchCtx();
+    *rc = init_ctx(c, device);
+    if (*rc != AES_OK) {
+        (void)hipGetLastError();
+        return nullptr;   // partially initialised context is leaked deliberately
+    }
+    g_ctx[key] = c;
+    return c;
+}
+
+// Capture (copy of slot s into the table) + kernel on a private stream.
+int build_graph(BatchCtx *c, int s, int grid, int bpl)
+{
+    SlotGraph &sg = c->g[s];
+    if (sg.exec) {
+        (void)hipGraphExecDestroy(sg.exec);
+        (void)hipGraphDestroy(sg.graph);
+        sg = SlotGraph{};
+    }
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return AES_EDEVICE;
+    int rc = AES_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = AES_EDEVICE;
+    } else {
+        (void)hipMemcpyAsync(c->dev_table, c->staging[s], kTableBytes, hipMemcpyHostToDevice, cap);
+        int lrc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, cap);
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(cap, &g) != hipSuccess || lrc != AES_OK || !g) {
+            rc = lrc != AES_OK ? lrc : AES_EDEVICE;
+        } else {
+            sg.graph = g;
+            size_t nn = 0;
+            (void)hipGraphGetNodes(g, nullptr, &nn);
+            std::vector<hipGraphNode_t> nodes(nn);
+            (void)hipGraphGetNodes(g, nodes.data(), &nn);
+            for (hipGraphNode_t nd : nodes) {
+                hipGraphNodeType ty;
+                if (hipGraphNodeGetType(nd, &ty) == hipSuccess && ty == hipGraphNodeTypeMemcpy)
+                    sg.copy_node = nd;
+            }
+            if (!sg.copy_node || hipGraphInstantiate(&sg.exec, g, nullptr, nullptr, 0) != hipSuccess)
+                rc = AES_EDEVICE;
+        }
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc != AES_OK) {
+        (void)hipGetLastError();
+        sg.exec = nullptr;
+        return rc;
+    }
+    sg.grid = grid;
+    sg.bpl = bpl;
+    return AES_OK;
+}
+
+// Fill staging slot `buf` with requests [first, first + n) and return the
+// number of bytes to upload.
+size_t stage(uint8_t *buf, const aes_ctr_desc_t *d, size_t n, uint32_t tile_blocks)
+{
+    BatchHeader *h = reinterpret_cast<BatchHeader *>(buf);
+    BatchDesc *out = reinterpret_cast<BatchDesc *>(buf + sizeof(BatchHeader));
+    uint64_t tiles = 0;
+    for (size_t i = 0; i < n; ++i) {
+        KeyMaterial km;
+        make_key_material(*d[i].sched, d[i].nonce, &km);
+        BatchDesc &o = out[i];
+        o.in = reinterpret_cast<uint64_t>(d[i].in);
+        o.out = reinterpret_cast<uint64_t>(d[i].out);
+        o.len = d[i].len;
+        o.ctr0 = d[i].ctr0;
+        o.x0 = km.x0;
+        o.nr = static_cast<uint32_t>(km.nr);
+        o.aligned = ((o.in | o.out) & 15) == 0;
+        memcpy(o.k1, km.k1, sizeof(o.k1));
+        o.tile0 = static_cast<uint32_t>(tiles);
+        memset(o.pad, 0, sizeof(o.pad));
+        memcpy(o.rk, km.rk, sizeof(o.rk));
+        const uint64_t blocks = (d[i].len + 15) / 16;
+        tiles += (blocks + tile_blocks - 1) / tile_blocks;
+    }
+    memset(h, 0, sizeof(*h));
+    h->n = static_cast<uint32_t>(n);
+    h->total_tiles = static_cast<uint32_t>(tiles);
+    h->tile_blocks = tile_blocks;
+    h->next = 0;
+    return sizeof(BatchHeader) + n * sizeof(BatchDesc);
+}
+
+}  // namespace
+
+}  // namespace aesctr
+
+using namespace aesctr;
+
+extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, const aes_batch_cfg_t *cfg,
+                                       void *stream)
+{
+    if (n == 0)
+        return AES_OK;
+    if (!desc)
+        return AES_EINVAL;
+    for (size_t i = 0; i < n; ++i) {
+        int rc = check_sched(desc[i].sched);
+        if (rc != AES_OK)
+            return rc;
+        if (desc[i].flags != 0)
+            return AES_EINVAL;
+        if ((rc = check_buffers(desc[i].in, desc[i].out, desc[i].len)) != AES_OK)
+            return rc;
+    }
+    BatchShape sh{16384, 1024, 0, 1, 1};
+    TuneEntry te;
+    if (tune_lookup_batch(&te)) {
+        sh.bpl = te.bpl;
+        sh.grid = 0;
+        if (te.copies > 0)   // the batch entry stores tile bytes in `copies`
+            sh.tile_bytes = te.copies;
+    }
+    if (cfg) {
+        if (cfg->tile_bytes < 0 || (cfg->tile_bytes && (cfg->tile_bytes % 1024 != 0 || cfg->tile_bytes > (1 << 26))))
+            return AES_EINVAL;
+        if (cfg->wg_size != 0 && cfg->wg_size != 1024)
+            return AES_EINVAL;
+        if (cfg->grid < 0 || (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2))
+            return AES_EINVAL;
+        if (cfg->tile_bytes) sh.tile_bytes = cfg->tile_bytes;
+        if (cfg->grid) sh.grid = cfg->grid;
+        if (cfg->blocks_per_lane) sh.bpl = cfg->blocks_per_lane;
+        sh.use_graph = cfg->use_graph;
+    }
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc != AES_OK)
+        return rc;
+    if (sh.grid == 0)
+        sh.grid = di.num_cus;
+    const uint32_t tile_blocks = static_cast<uint32_t>(sh.tile_bytes / 16);
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return AES_EDEVICE;
+    }
+    if (cs != hipStreamCaptureStatusNone)
+        return AES_EINVAL;
+
+    BatchCtx *c = get_ctx(di.ordinal, stream, &rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (size_t first = 0; first < n; first += kMaxBatch) {
+        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
+        const int slot = c->next_slot;
+        c->next_slot = (c->next_slot + 1) % kSlots;
+        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
+            (void)hipGetLastError();
+            return AES_EDEVICE;
+        }
+        const size_t bytes = stage(c->staging[slot], desc + first, m, tile_blocks);
+        if (sh.use_graph) {
+            SlotGraph &sg = c->g[slot];
+            if (!sg.exec || sg.grid != sh.grid || sg.bpl != sh.bpl) {
+                if ((rc = build_graph(c, slot, sh.grid, sh.bpl)) != AES_OK)
+                    return rc;
+            }
+            if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
+                                                  hipMemcpyHostToDevice) != hipSuccess ||
+                hipGraphLaunch(sg.exec, st) != hipSuccess) {
+                (void)hipGetLastError();
+                return AES_EDEVICE;
+            }
+        } else {
+            if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+                (void)hipGetLastError();
+                return AES_EDEVICE;
+            }
+            if ((rc = launch_ctr_batch(c->dev_table, sh.grid, 1024, sh.bpl, st)) != AES_OK)
+                return rc;
+        }
+        if (hipEventRecord(c->done[slot], st) != hipSuccess) {
+            (void)hipGetLastError();
+            return AES_EDEVICE;
+        }
+        c->used[slot] = true;
+    }
+    return AES_OK;
+}
+
+extern "C" int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream)
+{
+    return aes_ctr_crypt_batch_cfg(desc, n, nullptr, stream);
+}

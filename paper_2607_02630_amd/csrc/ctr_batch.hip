@@ -1,0 +1,175 @@
+// ctr_batch.hip -- one persistent launch over a table of requests (gfx950).
+//
+// Each workgroup fills the bank-replicated T-tables into LDS once (the same
+// round code as the single-buffer kernel, ttable_device.h), copies the
+// requests' first-tile indices into LDS, then its waves claim tiles from a
+// device counter until the table is exhausted.  A tile is tile_blocks
+// consecutive 16-byte blocks of one request; the wave finds the request by a
+// binary search over the tile indices in LDS and reads that request's key
+// material, pointers and counter parameters with scalar loads (they are the
+// same for the whole wave).  Requests of any size, key length (AES-128 and
+// AES-256 mixed) and alignment share the launch; dynamic claiming balances
+// the log-uniform size mix.
+#include <stddef.h>
+
+#include "ttable_device.h"
+
+namespace aesctr {
+namespace {
+
+constexpr int kBatchWG = 1024;
+constexpr int kBatchCopies = 32;
+
+// Request pointers arrive as integers; these types keep their accesses in the
+// global address space (global_load/store rather than flat).
+typedef __attribute__((address_space(1))) const u32x4 g_cu32x4;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+typedef __attribute__((address_space(1))) const uint8_t g_cu8;
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+
+template <int NR, int BPL, bool ALIGNED>
+__device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const CtrArgs &a, uint64_t b0,
+                                         uint64_t b1, uint32_t lane)
+{
+    const uint64_t nfull = a.len >> 4;
+    uint32_t krot[1];   // unused by the 32-copy table
+    for (uint64_t base = b0 + lane; base < b1; base += 64 * BPL) {
+        uint32_t ctr[BPL], ks[BPL][4];
+        u32x4 d[BPL];
+#pragma unroll
+        for (int b = 0; b < BPL; ++b) {
+            const uint64_t idx = base + 64 * b;
+            ctr[b] = a.ctr0 + static_cast<uint32_t>(idx);
+            if (idx < nfull) {
+                if constexpr (ALIGNED) {
+                    d[b] = __builtin_nontemporal_load((g_cu32x4 *)(uintptr_t)a.in + idx);
+                } else {
+                    g_cu8 *p = (g_cu8 *)(uintptr_t)a.in + 16 * idx;
+                    uint8_t tmp[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) tmp[i] = p[i];
+                    __builtin_memcpy(&d[b], tmp, 16);
+                }
+            }
+        }
+        keystream<NR, kBatchCopies, BPL>(tt, a, krot, ctr, ks);
+#pragma unroll
+        for (int b = 0; b < BPL; ++b) {
+            const uint64_t idx = base + 64 * b;
+            const u32x4 k = u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]};
+            if (idx < nfull) {
+                if constexpr (ALIGNED) {
+                    __builtin_nontemporal_store(d[b] ^ k, (g_u32x4 *)(uintptr_t)a.out + idx);
+                } else {
+                    const u32x4 v = d[b] ^ k;
+                    uint8_t tmp[16];
+                    __builtin_memcpy(tmp, &v, 16);
+                    g_u8 *p = (g_u8 *)(uintptr_t)a.out + 16 * idx;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) p[i] = tmp[i];
+                }
+            } else if (idx == nfull && idx < b1) {
+                // Final partial block: leading bytes of its keystream block.
+                const uint32_t tail = static_cast<uint32_t>(a.len & 15);
+                g_cu8 *src = (g_cu8 *)(uintptr_t)a.in + 16 * idx;
+                g_u8 *dst = (g_u8 *)(uintptr_t)a.out + 16 * idx;
+                for (uint32_t i = 0; i < tail; ++i)
+                    dst[i] = src[i] ^ static_cast<uint8_t>(k[i >> 2] >> (8 * (i & 3)));
+            }
+        }
+    }
+}
+
+// table: the uploaded header + descriptors, read-only here (so request fields
+// come in through the scalar cache); counter: the header's `next` word, the
+// only thing the kernel writes besides the outputs.
+template <int BPL>
+__global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__restrict__ table,
+                                                             uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t lds[kLdsWords];
+    __shared__ uint32_t s_tile0[kMaxBatch];
+
+    const BatchHeader *hdr = reinterpret_cast<const BatchHeader *>(table);
+    const BatchDesc *desc = reinterpret_cast<const BatchDesc *>(table + sizeof(BatchHeader));
+    const uint32_t n = hdr->n;
+    const uint32_t total = hdr->total_tiles;
+    const uint32_t tile_blocks = hdr->tile_blocks;
+
+    uint32_t tv[kFillStores / kBatchWG];
+    fill_read<kBatchWG>(tv);
+    for (uint32_t i = threadIdx.x; i < n; i += kBatchWG)
+        s_tile0[i] = desc[i].tile0;
+    fill_write<kBatchCopies, kBatchWG>(lds, tv);
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & 63;
+    TTable<kBatchCopies> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
+
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0)
+            t = atomicAdd(counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= total)
+            break;
+        // Last request whose first tile is <= t (empty requests share their
+        // successor's tile0 and are skipped by taking the last match).
+        uint32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_tile0[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
+        const BatchDesc *R = desc + r;
+        CtrArgs a;
+        a.in = reinterpret_cast<const uint8_t *>(R->in);
+        a.out = reinterpret_cast<uint8_t *>(R->out);
+        a.len = R->len;
+        a.ctr0 = R->ctr0;
+        a.x0 = R->x0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            a.k1[c] = R->k1[c];
+        const uint32_t nr = R->nr;
+        const uint32_t nrk = 4 * (nr + 1);
+#pragma unroll
+        for (int i = 0; i < 60; ++i)
+            a.rk[i] = i < 44 || nrk > 44 ? R->rk[i] : 0;
+        const uint64_t nblocks = (a.len + 15) >> 4;
+        const uint64_t b0 = static_cast<uint64_t>(t - R->tile0) * tile_blocks;
+        const uint64_t b1 = b0 + tile_blocks < nblocks ? b0 + tile_blocks : nblocks;
+        if (R->aligned) {
+            if (nr == 10)
+                run_tile<10, BPL, true>(tt, a, b0, b1, lane);
+            else
+                run_tile<14, BPL, true>(tt, a, b0, b1, lane);
+        } else {
+            if (nr == 10)
+                run_tile<10, BPL, false>(tt, a, b0, b1, lane);
+            else
+                run_tile<14, BPL, false>(tt, a, b0, b1, lane);
+        }
+    }
+}
+
+}  // namespace
+
+int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream_t st)
+{
+    if (wg != kBatchWG || grid <= 0)
+        return AES_EINVAL;
+    const uint8_t *t = static_cast<const uint8_t *>(dev_table);
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(const_cast<uint8_t *>(t) + offsetof(BatchHeader, next));
+    switch (bpl) {
+    case 1: hipLaunchKernelGGL(ctr_batch_kernel<1>, dim3(grid), dim3(kBatchWG), 0, st, t, ctr); break;
+    case 2: hipLaunchKernelGGL(ctr_batch_kernel<2>, dim3(grid), dim3(kBatchWG), 0, st, t, ctr); break;
+    default: return AES_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? AES_OK : AES_EDEVICE;
+}
+
+}  // namespace aesctr

@@ -1,0 +1,194 @@
+// ctr_ttable.hip -- AES-CTR keystream + XOR with round T-tables in LDS (gfx950).
+//
+// One lane encrypts one 16-byte counter block per loop step (BPL of them
+// interleaved for latency hiding); a workgroup covers a contiguous chunk of
+// wg * BPL blocks, so every global load/store instruction moves 64
+// consecutive 16-byte blocks (1 KiB per wave, dwordx4 per lane).  The round
+// function and the LDS table layout are in ttable_device.h.
+#include "ttable_device.h"
+
+namespace aesctr {
+namespace {
+
+template <bool ALIGNED>
+__device__ __forceinline__ u32x4 load_block(const u32x4 *src, uint64_t idx)
+{
+    if constexpr (ALIGNED) {
+        return __builtin_nontemporal_load(src + idx);
+    } else {
+        u32x4 d;
+        __builtin_memcpy(&d, reinterpret_cast<const uint8_t *>(src) + 16 * idx, 16);
+        return d;
+    }
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ void store_block(const CtrArgs &a, uint64_t idx, u32x4 v)
+{
+    if constexpr (ALIGNED) {
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(a.out) + idx);
+    } else {
+        __builtin_memcpy(a.out + 16 * idx, &v, 16);
+    }
+}
+
+template <bool ALIGNED, int BPL>
+__device__ __forceinline__ void prefetch(const u32x4 *src, uint64_t base, uint64_t wg, uint64_t nfull,
+                                         uint64_t last, u32x4 (&d)[BPL])
+{
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        const uint64_t idx = base + b * wg;
+        d[b] = load_block<ALIGNED>(src, idx < nfull ? idx : last);
+    }
+}
+
+// Keystream of the chunk at `start` XORed into the data d already loaded.
+template <int NR, int COPIES, int BPL, bool ALIGNED>
+__device__ __forceinline__ void chunk_step(const TTable<COPIES> &tt, const CtrArgs &a, const uint32_t *krot,
+                                           uint64_t start, uint64_t wg, uint64_t nfull, const u32x4 (&d)[BPL])
+{
+    const uint64_t base = start + threadIdx.x;
+    uint32_t ctr[BPL], ks[BPL][4];
+#pragma unroll
+    for (int b = 0; b < BPL; ++b)
+        ctr[b] = a.ctr0 + static_cast<uint32_t>(base + b * wg);
+    keystream<NR, COPIES, BPL>(tt, a, krot, ctr, ks);
+    if (start + wg * BPL <= nfull) {
+#pragma unroll
+        for (int b = 0; b < BPL; ++b)
+            store_block<ALIGNED>(a, base + b * wg, d[b] ^ u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]});
+    } else {
+#pragma unroll
+        for (int b = 0; b < BPL; ++b) {
+            const uint64_t idx = base + b * wg;
+            if (idx < nfull)
+                store_block<ALIGNED>(a, idx, d[b] ^ u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]});
+        }
+    }
+}
+
+// Loop step over a workgroup chunk of wg * BPL blocks: thread t handles
+// blocks base + t + b * wg.  The loads of the next chunk are issued before
+// this chunk's keystream is computed (the keystream does not depend on the
+// data), so HBM latency hides behind the table lookups.
+template <int NR, int COPIES, int BPL, int WG, bool ALIGNED>
+__global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
+{
+    __shared__ uint32_t lds[kLdsWords];
+
+    const uint64_t nfull = a.len >> 4;
+    const uint64_t wg = WG;
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * wg * BPL;
+    uint64_t start = static_cast<uint64_t>(blockIdx.x) * wg * BPL;
+
+    // Table reads first, then the first chunk's data, so the LDS writes wait
+    // only for the (cached) table reads while the data is still in flight.
+    // Out-of-range lanes load a clamped (valid) block and never store it, so
+    // no branch separates these loads from the table reads (a branch would
+    // make the compiler wait for every load before the LDS writes).  With no
+    // whole block at all, the loads read a dummy block instead.
+    uint32_t tv[kFillStores / WG];
+    fill_read<WG>(tv);
+    const uint64_t last = nfull ? nfull - 1 : 0;
+    const u32x4 *src = nfull ? reinterpret_cast<const u32x4 *>(a.in) : &g_dummy_block;
+    u32x4 d[BPL];
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        const uint64_t idx = start + threadIdx.x + b * wg;
+        d[b] = load_block<ALIGNED>(src, idx < nfull ? idx : last);
+    }
+    fill_write<COPIES, WG>(lds, tv);
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t k = COPIES == 32 ? (lane & 31) : lane;
+    TTable<COPIES> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
+
+    // rotr(rk, 8) for the two-table fold; uniform, lives in scalar registers.
+    uint32_t krot[60];
+    if constexpr (COPIES == 64) {
+#pragma unroll
+        for (int i = 0; i < 4 * (NR + 1); ++i) krot[i] = (a.rk[i] >> 8) | (a.rk[i] << 24);
+    }
+
+    // The first chunk is peeled off so no loop-header wait delays it; then
+    // two chunks per trip with the data buffers swapping roles, so no
+    // register copy forces an early wait on the loads in flight.
+    u32x4 e[BPL];
+    if (start < nfull) {
+        prefetch<ALIGNED, BPL>(src, start + step + threadIdx.x, wg, nfull, last, e);
+        chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, wg, nfull, d);
+        start += step;
+        while (start < nfull) {
+            prefetch<ALIGNED, BPL>(src, start + step + threadIdx.x, wg, nfull, last, d);
+            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, wg, nfull, e);
+            start += step;
+            if (!(start < nfull))
+                break;
+            prefetch<ALIGNED, BPL>(src, start + step + threadIdx.x, wg, nfull, last, e);
+            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, wg, nfull, d);
+            start += step;
+        }
+    }
+
+    // Final partial block: leading bytes of its keystream block.
+    const uint32_t tail = static_cast<uint32_t>(a.len & 15);
+    if (tail != 0 && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        uint32_t ctr1[1] = {a.ctr0 + static_cast<uint32_t>(nfull)};
+        uint32_t ks[1][4];
+        keystream<NR, COPIES, 1>(tt, a, krot, ctr1, ks);
+        const uint64_t off = 16 * nfull;
+        for (uint32_t i = 0; i < tail; ++i)
+            a.out[off + i] = a.in[off + i] ^ static_cast<uint8_t>(ks[0][i >> 2] >> (8 * (i & 3)));
+    }
+}
+
+template <int NR, int COPIES, int BPL, int WG>
+int launch_w(const CtrArgs &a, const Shape &sh, hipStream_t st)
+{
+    const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
+    if (aligned)
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, COPIES, BPL, WG, true>), dim3(sh.grid), dim3(WG), 0, st, a);
+    else
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, COPIES, BPL, WG, false>), dim3(sh.grid), dim3(WG), 0, st, a);
+    return hipGetLastError() == hipSuccess ? AES_OK : AES_EDEVICE;
+}
+
+template <int NR, int COPIES, int BPL>
+int launch_t(const CtrArgs &a, const Shape &sh, hipStream_t st)
+{
+    switch (sh.wg) {
+    case 256: return launch_w<NR, COPIES, BPL, 256>(a, sh, st);
+    case 512: return launch_w<NR, COPIES, BPL, 512>(a, sh, st);
+    case 1024: return launch_w<NR, COPIES, BPL, 1024>(a, sh, st);
+    default: return AES_EINVAL;
+    }
+}
+
+template <int NR, int COPIES>
+int launch_b(const CtrArgs &a, const Shape &sh, hipStream_t st)
+{
+    switch (sh.bpl) {
+    case 1: return launch_t<NR, COPIES, 1>(a, sh, st);
+    case 2: return launch_t<NR, COPIES, 2>(a, sh, st);
+    case 4: return launch_t<NR, COPIES, 4>(a, sh, st);
+    default: return AES_EINVAL;
+    }
+}
+
+}  // namespace
+
+int launch_ctr_ttable(const CtrArgs &a, int nr, const Shape &sh, hipStream_t st)
+{
+    // The LDS fill splits 8192 stores evenly over the workgroup.
+    if ((sh.wg != 256 && sh.wg != 512 && sh.wg != 1024) || sh.grid <= 0)
+        return AES_EINVAL;
+    if (nr == 10)
+        return sh.copies == 64 ? launch_b<10, 64>(a, sh, st) : sh.copies == 32 ? launch_b<10, 32>(a, sh, st) : AES_EINVAL;
+    if (nr == 14)
+        return sh.copies == 64 ? launch_b<14, 64>(a, sh, st) : sh.copies == 32 ? launch_b<14, 32>(a, sh, st) : AES_EINVAL;
+    return AES_EINVAL;
+}
+
+}  // namespace aesctr

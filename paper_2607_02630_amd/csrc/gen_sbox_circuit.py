@@ -1,0 +1,575 @@
+#!/usr/bin/env python3
+"""Generate the bitsliced AES S-box circuit used by the bitsliced kernel.
+
+The S-box of FIPS-197 Sec. 5.1.1 is S(x) = A(x^-1) + {63}, with the inverse
+taken in GF(2^8) modulo x^8 + x^4 + x^3 + x + 1.  A boolean circuit for it is
+derived here from the field arithmetic alone (no table is typed in):
+
+1. Represent GF(2^8) as a tower GF(((2^2)^2)^2):
+     GF(4)   = GF(2)[v]/(v^2 + v + 1)
+     GF(16)  = GF(4)[w]/(w^2 + w + nu)      nu in GF(4), polynomial irreducible
+     GF(256) = GF(16)[y]/(y^2 + y + lam)    lam in GF(16), polynomial irreducible
+   and map the AES field into it by the GF(2)-linear isomorphism sending x
+   to a root beta of the AES polynomial (Canright, "A very compact Rijndael
+   S-box", 2005, takes the same route).
+2. Invert in the tower with the norm formula for a quadratic extension:
+     (a y + b)^-1 = a D^-1 y + (a + b) D^-1,   D = lam a^2 + a b + b^2
+   applied twice (GF(256) over GF(16), GF(16) over GF(4)); in GF(4) the
+   inverse is squaring.  Products use Karatsuba, 3 sub-products each, so the
+   whole inversion has 36 AND gates; everything else is GF(2)-linear.
+3. Every linear signal is a XOR of "basis" signals (the 8 input bits and the
+   AND outputs).  The XORs needed are shared greedily (Paar's algorithm,
+   "A new algorithm for constructing small XOR circuits", 1997).
+4. The 2-input netlist is covered with 3-input functions: a gate whose only
+   reader can absorb it (at most 3 distinct leaves) is merged into that
+   reader.  Each 3-input node becomes one v_bitop3_b32 with its truth table.
+   The affine constant {63} is folded into the output nodes' truth tables.
+
+The search over (nu, lam, beta) keeps the smallest circuit.  The result is
+checked on all 256 inputs against the S-box computed from its definition,
+and written as straight-line C++ to sbox_circuit.inc.
+
+Usage: python gen_sbox_circuit.py [--out sbox_circuit.inc]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import os
+from collections import Counter
+
+# --------------------------------------------------------------------------
+# Field arithmetic (value level)
+# --------------------------------------------------------------------------
+
+
+def aes_mul(a: int, b: int) -> int:
+    r = 0
+    while b:
+        if b & 1:
+            r ^= a
+        a <<= 1
+        if a & 0x100:
+            a ^= 0x11B
+        b >>= 1
+    return r
+
+
+def aes_sbox_table() -> list[int]:
+    inv = [0] * 256
+    for a in range(1, 256):
+        for b in range(1, 256):
+            if aes_mul(a, b) == 1:
+                inv[a] = b
+                break
+    out = []
+    for x in range(256):
+        b = inv[x]
+        s = 0
+        for i in range(8):
+            bit = ((b >> i) ^ (b >> ((i + 4) % 8)) ^ (b >> ((i + 5) % 8)) ^
+                   (b >> ((i + 6) % 8)) ^ (b >> ((i + 7) % 8)) ^ (0x63 >> i)) & 1
+            s |= bit << i
+        out.append(s)
+    return out
+
+
+def g4_mul(a: int, b: int) -> int:
+    a1, a0, b1, b0 = a >> 1, a & 1, b >> 1, b & 1
+    m1, m0, m2 = a1 & b1, a0 & b0, (a1 ^ a0) & (b1 ^ b0)
+    return ((m2 ^ m0) << 1) | (m1 ^ m0)
+
+
+def g16_mul(a: int, b: int, nu: int) -> int:
+    A1, A0, B1, B0 = a >> 2, a & 3, b >> 2, b & 3
+    M1, M0, M2 = g4_mul(A1, B1), g4_mul(A0, B0), g4_mul(A1 ^ A0, B1 ^ B0)
+    return ((M2 ^ M0) << 2) | (g4_mul(nu, M1) ^ M0)
+
+
+def g256_mul(a: int, b: int, nu: int, lam: int) -> int:
+    A1, A0, B1, B0 = a >> 4, a & 15, b >> 4, b & 15
+    M1, M0, M2 = g16_mul(A1, B1, nu), g16_mul(A0, B0, nu), g16_mul(A1 ^ A0, B1 ^ B0, nu)
+    return ((M2 ^ M0) << 4) | (g16_mul(lam, M1, nu) ^ M0)
+
+
+def irreducible_quadratic(c: int, mul, size: int) -> bool:
+    """t^2 + t + c has no root in a field of `size` elements."""
+    return all((mul(t, t) ^ t) != c for t in range(size))
+
+
+def tower_roots_of_aes_poly(nu: int, lam: int) -> list[int]:
+    roots = []
+    for beta in range(2, 256):
+        p = [1]
+        for _ in range(8):
+            p.append(g256_mul(p[-1], beta, nu, lam))
+        # beta^8 + beta^4 + beta^3 + beta + 1
+        if p[8] ^ p[4] ^ p[3] ^ p[1] ^ 1 == 0:
+            roots.append(beta)
+    return roots
+
+
+# --------------------------------------------------------------------------
+# GF(2) matrices as lists of row bitmasks
+# --------------------------------------------------------------------------
+
+
+def mat_from_columns(cols: list[int], n: int = 8) -> list[int]:
+    rows = [0] * n
+    for j, col in enumerate(cols):
+        for i in range(n):
+            if (col >> i) & 1:
+                rows[i] |= 1 << j
+    return rows
+
+
+def mat_vec(rows: list[int], v: int) -> int:
+    out = 0
+    for i, r in enumerate(rows):
+        out |= (bin(r & v).count("1") & 1) << i
+    return out
+
+
+def mat_inv(rows: list[int], n: int = 8) -> list[int]:
+    a = [(rows[i], 1 << i) for i in range(n)]
+    for c in range(n):
+        piv = next(i for i in range(c, n) if (a[i][0] >> c) & 1)
+        a[c], a[piv] = a[piv], a[c]
+        for i in range(n):
+            if i != c and (a[i][0] >> c) & 1:
+                a[i] = (a[i][0] ^ a[c][0], a[i][1] ^ a[c][1])
+    return [a[i][1] for i in range(n)]
+
+
+def mat_mul(x: list[int], y: list[int], n: int = 8) -> list[int]:
+    cols_y = [sum(((y[i] >> j) & 1) << i for i in range(n)) for j in range(n)]
+    return [sum((bin(x[i] & cols_y[j]).count("1") & 1) << j for j in range(n)) for i in range(n)]
+
+
+# --------------------------------------------------------------------------
+# Symbolic circuit: linear forms over basis variables + AND gates
+# --------------------------------------------------------------------------
+
+
+class Sym:
+    """Signals are frozensets of basis variables (their XOR).  Basis
+    variables 0..7 are the input bits; each AND adds a variable."""
+
+    def __init__(self):
+        self.nvars = 8
+        self.ands: list[tuple[frozenset, frozenset]] = []   # var 8+k = ands[k][0] & ands[k][1]
+
+    @staticmethod
+    def xor(a: frozenset, b: frozenset) -> frozenset:
+        return a ^ b
+
+    def and_(self, a: frozenset, b: frozenset) -> frozenset:
+        if not a or not b:
+            return frozenset()
+        self.ands.append((a, b))
+        v = self.nvars
+        self.nvars += 1
+        return frozenset([v])
+
+    # GF(4) element: (hi, lo) forms
+    def g4_mul(self, a, b):
+        m1 = self.and_(a[0], b[0])
+        m0 = self.and_(a[1], b[1])
+        m2 = self.and_(a[0] ^ a[1], b[0] ^ b[1])
+        return (m2 ^ m0, m1 ^ m0)
+
+    @staticmethod
+    def g4_sq(a):
+        return (a[0], a[0] ^ a[1])
+
+    @staticmethod
+    def g4_mulconst(c: int, a):
+        # multiply (a1 v + a0) by a constant of GF(4), linearly
+        cols = [g4_mul(c, 1), g4_mul(c, 2)]        # images of basis 1 and v
+        hi = frozenset()
+        lo = frozenset()
+        for bitval, form in ((1, a[1]), (2, a[0])):
+            img = cols[0] if bitval == 1 else cols[1]
+            if img & 2:
+                hi = hi ^ form
+            if img & 1:
+                lo = lo ^ form
+        return (hi, lo)
+
+    # GF(16) element: (A1, A0) GF(4) elements
+    def g16_mul(self, a, b, nu):
+        M1 = self.g4_mul(a[0], b[0])
+        M0 = self.g4_mul(a[1], b[1])
+        M2 = self.g4_mul(add4(a[0], a[1]), add4(b[0], b[1]))
+        return (add4(M2, M0), add4(self.g4_mulconst(nu, M1), M0))
+
+    def g16_linear(self, a, fn):
+        """Apply a GF(2)-linear map on GF(16) given as a function on values."""
+        bits = [a[1][1], a[1][0], a[0][1], a[0][0]]   # value bits 0..3: lo.lo, lo.hi, hi.lo, hi.hi
+        out = [frozenset()] * 4
+        for i in range(4):
+            img = fn(1 << i)
+            for j in range(4):
+                if (img >> j) & 1:
+                    out[j] = out[j] ^ bits[i]
+        return ((out[3], out[2]), (out[1], out[0]))
+
+    def g16_inv(self, d, nu):
+        D1, D0 = d
+        t = add4(add4(self.g4_mulconst(nu, self.g4_sq(D1)), self.g4_mul(D1, D0)), self.g4_sq(D0))
+        ti = self.g4_sq(t)
+        return (self.g4_mul(D1, ti), self.g4_mul(add4(D1, D0), ti))
+
+
+def add4(a, b):
+    return (a[0] ^ b[0], a[1] ^ b[1])
+
+
+def add16(a, b):
+    return (add4(a[0], b[0]), add4(a[1], b[1]))
+
+
+def value_bits_to_g16(bits):   # bits[0..3] -> GF(16) symbolic element
+    return ((bits[3], bits[2]), (bits[1], bits[0]))
+
+
+def g16_to_bits(e):
+    return [e[1][1], e[1][0], e[0][1], e[0][0]]
+
+
+def build_inverse(nu: int, lam: int, to_tower: list[int], from_tower_affine: list[int]):
+    """Symbolic S-box: returns (Sym, list of 8 output forms)."""
+    S = Sym()
+    x = [frozenset([i]) for i in range(8)]
+    # tower bits t_i = XOR_j to_tower[i]_j x_j
+    t = []
+    for i in range(8):
+        f = frozenset()
+        for j in range(8):
+            if (to_tower[i] >> j) & 1:
+                f = f ^ x[j]
+        t.append(f)
+    A = value_bits_to_g16(t[4:8])     # coefficient of y
+    B = value_bits_to_g16(t[0:4])
+    sq_lam = S.g16_linear(A, lambda v: g16_mul(lam, g16_mul(v, v, nu), nu))
+    sq_b = S.g16_linear(B, lambda v: g16_mul(v, v, nu))
+    D = add16(add16(sq_lam, S.g16_mul(A, B, nu)), sq_b)
+    Di = S.g16_inv(D, nu)
+    C = S.g16_mul(A, Di, nu)
+    E = S.g16_mul(add16(A, B), Di, nu)
+    inv_bits = g16_to_bits(E) + g16_to_bits(C)      # tower value bits 0..7
+    outs = []
+    for i in range(8):
+        f = frozenset()
+        for j in range(8):
+            if (from_tower_affine[i] >> j) & 1:
+                f = f ^ inv_bits[j]
+        outs.append(f)
+    return S, outs
+
+
+# --------------------------------------------------------------------------
+# Netlist: Paar XOR sharing, then 3-input covering
+# --------------------------------------------------------------------------
+
+
+class Node:
+    __slots__ = ("op", "ins", "tt")
+
+    def __init__(self, op, ins, tt=None):
+        self.op, self.ins, self.tt = op, list(ins), tt
+
+
+def paar(forms: list[set], next_var: int, new_xor, rng=None):
+    """Greedy pair sharing; mutates forms until each is one variable.  Ties
+    between equally frequent pairs are broken by `rng` (or by index)."""
+    while True:
+        cnt = Counter()
+        for f in forms:
+            if len(f) >= 2:
+                for p in itertools.combinations(sorted(f), 2):
+                    cnt[p] += 1
+        if not cnt:
+            return next_var
+        top = max(cnt.values())
+        ties = sorted(p for p, c in cnt.items() if c == top)
+        a, b = rng.choice(ties) if rng is not None else ties[0]
+        v = next_var
+        next_var += 1
+        new_xor(v, a, b)
+        for f in forms:
+            if a in f and b in f:
+                f.discard(a)
+                f.discard(b)
+                f.add(v)
+
+
+def build_netlist(S: Sym, outs: list[frozenset], rng=None):
+    """2-input netlist in topological order.  Returns (nodes, out_vars)."""
+    nodes: dict[int, Node] = {}
+    order: list[int] = []
+
+    # Forms to materialise: every AND input, every output.
+    and_in = []
+    for a, b in S.ands:
+        and_in.append(set(a))
+        and_in.append(set(b))
+    out_forms = [set(o) for o in outs]
+    forms = and_in + out_forms
+    var_of_form_index = {}
+
+    def new_xor(v, a, b):
+        nodes[v] = Node("xor", (a, b))
+
+    next_var = paar(forms, S.nvars, new_xor, rng)
+    for k, (a, b) in enumerate(S.ands):
+        fa, fb = forms[2 * k], forms[2 * k + 1]
+        assert len(fa) == 1 and len(fb) == 1
+        nodes[8 + k] = Node("and", (next(iter(fa)), next(iter(fb))))
+    out_vars = []
+    for f in forms[len(and_in):]:
+        assert len(f) == 1
+        out_vars.append(next(iter(f)))
+
+    # Topological order by dependency.
+    seen = set(range(8))
+
+    def visit(v):
+        if v in seen:
+            return
+        for u in nodes[v].ins:
+            visit(u)
+        seen.add(v)
+        order.append(v)
+
+    for v in out_vars:
+        visit(v)
+    del next_var, var_of_form_index
+    return nodes, order, out_vars
+
+
+def cover_lut3(nodes: dict[int, Node], order: list[int], out_vars: list[int]):
+    """Cover the 2-input netlist with 3-input functions (cut-based mapping
+    with area flow, as in LUT technology mapping).  Returns
+    {var: (leaves, truth table over leaves)} for the chosen nodes."""
+    fanout = Counter()
+    for v in order:
+        for u in nodes[v].ins:
+            fanout[u] += 1
+    for v in out_vars:
+        fanout[v] += 1
+    cuts: dict[int, list[frozenset]] = {i: [frozenset([i])] for i in range(8)}
+    af: dict[int, float] = {i: 0.0 for i in range(8)}
+    best_cut: dict[int, frozenset] = {}
+    for v in order:
+        a, b = nodes[v].ins
+        cs = set()
+        for ca in cuts[a]:
+            for cb in cuts[b]:
+                u = ca | cb
+                if len(u) <= 3:
+                    cs.add(u)
+        def flow(c):
+            return 1.0 + sum(af[u] / max(fanout[u], 1) for u in c)
+        ranked = sorted(cs, key=lambda c: (flow(c), len(c), sorted(c)))
+        best_cut[v] = ranked[0]
+        af[v] = flow(ranked[0])
+        cuts[v] = [frozenset([v])] + ranked[:12]
+
+    def truth_table(v, leaves):
+        tt = {}
+        for bits in itertools.product((0, 1), repeat=len(leaves)):
+            env = dict(zip(leaves, bits))
+
+            def ev(x):
+                if x in env:
+                    return env[x]
+                n = nodes[x]
+                l, r = ev(n.ins[0]), ev(n.ins[1])
+                return l ^ r if n.op == "xor" else l & r
+            tt[bits] = ev(v)
+        return tt
+
+    # Select the cover from the outputs down; then recover area by
+    # re-choosing each selected node's cut with exact (cover-aware) cost.
+    def select(choice):
+        chosen, stack = set(), list(out_vars)
+        while stack:
+            v = stack.pop()
+            if v < 8 or v in chosen:
+                continue
+            chosen.add(v)
+            stack.extend(choice[v])
+        return chosen
+
+    choice = dict(best_cut)
+    chosen = select(choice)
+    for _ in range(4):
+        improved = False
+        for v in order:
+            if v not in chosen:
+                continue
+            cur = len(chosen)
+            for c in cuts[v][1:]:
+                if c == choice[v]:
+                    continue
+                trial = dict(choice)
+                trial[v] = c
+                n = len(select(trial))
+                if n < cur:
+                    choice, cur, improved = trial, n, True
+            chosen = select(choice)
+        if not improved:
+            break
+    lut = {}
+    for v in order:
+        if v in chosen:
+            leaves = sorted(choice[v])
+            lut[v] = (leaves, truth_table(v, leaves))
+    return lut
+
+
+def evaluate(lut, order, out_vars, invert_mask, inputs):
+    val = dict(enumerate(inputs))
+    full = (1 << 256) - 1
+    for v in order:
+        if v not in lut:
+            continue
+        leaves, tt = lut[v]
+        acc = 0
+        for bits, o in tt.items():
+            if not o:
+                continue
+            term = full
+            for leaf, b in zip(leaves, bits):
+                term &= val[leaf] if b else (~val[leaf] & full)
+            acc |= term
+        val[v] = acc
+    outs = []
+    for i, v in enumerate(out_vars):
+        x = val[v]
+        if (invert_mask >> i) & 1:
+            x = ~x & full
+        outs.append(x)
+    return outs
+
+
+def bitsliced_inputs():
+    return [sum(((x >> b) & 1) << x for x in range(256)) for b in range(8)]
+
+
+def synthesize(nu, lam, beta, rng=None):
+    # to_tower: columns = tower value of beta^j (image of AES basis x^j)
+    cols = []
+    p = 1
+    for _ in range(8):
+        cols.append(p)
+        p = g256_mul(p, beta, nu, lam)
+    to_std_cols = cols                       # maps AES-basis coords -> tower value bits
+    to_tower = mat_from_columns(to_std_cols)
+    from_tower = mat_inv(to_tower)
+    # affine matrix: b'_i = b_i ^ b_{i+4} ^ b_{i+5} ^ b_{i+6} ^ b_{i+7}
+    aff = [0] * 8
+    for i in range(8):
+        for k in (0, 4, 5, 6, 7):
+            aff[i] |= 1 << ((i + k) % 8)
+    out_mat = mat_mul(aff, from_tower)
+    S, outs = build_inverse(nu, lam, to_tower, out_mat)
+    nodes, order, out_vars = build_netlist(S, outs, rng)
+    lut = cover_lut3(nodes, order, out_vars)
+    return lut, order, out_vars
+
+
+def search(seeds: int = 0):
+    """Try every tower (nu, lam, beta); for each, index tie-breaking plus
+    `seeds` seeded random tie-breakings of the XOR sharing."""
+    import random
+    table = aes_sbox_table()
+    best = None
+    for nu in (2, 3):
+        if not irreducible_quadratic(nu, g4_mul, 4):
+            continue
+        for lam in range(1, 16):
+            if not irreducible_quadratic(lam, lambda a, b: g16_mul(a, b, nu), 16):
+                continue
+            for beta, seed in itertools.product(tower_roots_of_aes_poly(nu, lam), range(-1, seeds)):
+                rng = random.Random(seed) if seed >= 0 else None
+                lut, order, out_vars = synthesize(nu, lam, beta, rng)
+                # Outputs must be distinct LUT nodes (no plain input passthrough).
+                if len(set(out_vars)) != 8 or any(v < 8 for v in out_vars):
+                    continue
+                outs = evaluate(lut, order, out_vars, 0x63, bitsliced_inputs())
+                got = [sum(((outs[b] >> x) & 1) << b for b in range(8)) for x in range(256)]
+                if got != table:
+                    raise AssertionError(f"circuit wrong for nu={nu} lam={lam} beta={beta}")
+                cost = len(lut)
+                if best is None or cost < best[0]:
+                    best = (cost, nu, lam, beta, lut, order, out_vars, seed)
+    return best
+
+
+def emit(best, path):
+    cost, nu, lam, beta, lut, order, out_vars, seed = best
+    names = {i: f"x[{i}]" for i in range(8)}
+    lines = []
+    tmp = 0
+    outpos = {v: i for i, v in enumerate(out_vars)}
+    body = []
+    for v in order:
+        if v not in lut:
+            continue
+        leaves, tt = lut[v]
+        pad = leaves + [leaves[-1]] * (3 - len(leaves))
+        # bitop3 truth table: bit index = (a << 2) | (b << 1) | c
+        code = 0
+        for a, b, c in itertools.product((0, 1), repeat=3):
+            env = {pad[0]: a, pad[1]: b, pad[2]: c}
+            if len({pad[0], pad[1], pad[2]}) < 3 and not all(
+                    env.get(x) is not None for x in pad):
+                pass
+            consistent = all(env[pad[i]] == (a, b, c)[i] for i in range(3))
+            if not consistent:
+                continue
+            bits = tuple(env[x] for x in leaves)
+            o = tt[bits]
+            if v in outpos and (0x63 >> outpos[v]) & 1:
+                o ^= 1
+            if o:
+                code |= 1 << ((a << 2) | (b << 1) | c)
+        if v in outpos:
+            name = f"o{outpos[v]}"
+        else:
+            name = f"t{tmp}"
+            tmp += 1
+        names[v] = name
+        args = ", ".join(names[x] for x in pad)
+        body.append(f"    const uint32_t {name} = bitop3({args}, 0x{code:02x});")
+    hdr = [
+        "// sbox_circuit.inc -- generated by gen_sbox_circuit.py; do not edit.",
+        "// Bitsliced AES S-box (FIPS-197 Sec. 5.1.1) as a straight-line program of",
+        f"// {cost} three-input boolean functions (v_bitop3_b32), derived from the",
+        f"// tower field GF(((2^2)^2)^2) with nu={nu}, lambda={lam}, beta={beta}",
+        f"// (XOR-sharing tie-break seed {seed}).",
+        "// x[b] holds bit b (LSB = 0) of 32 bytes; on return x[b] holds bit b of",
+        "// their S-box values.  bitop3(a, b, c, T) must compute the function whose",
+        "// value for inputs (a, b, c) is bit (a<<2 | b<<1 | c) of T.",
+    ]
+    tail = [f"    x[{i}] = o{i};" for i in range(8)]
+    with open(path, "w") as f:
+        f.write("\n".join(hdr + ["{"] + body + tail + ["}"]) + "\n")
+    return cost
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--seeds", type=int, default=24)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  "sbox_circuit.inc"))
+    args = ap.parse_args()
+    best = search(args.seeds)
+    cost = emit(best, args.out)
+    print(f"S-box circuit: {cost} bitop3 nodes (nu={best[1]} lam={best[2]} beta={best[3]}) -> {args.out}")
+
+
+if __name__ == "__main__":
+    main()

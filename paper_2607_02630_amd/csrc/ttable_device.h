@@ -1,0 +1,196 @@
+// ttable_device.h -- device code of the T-table AES round shared by the
+// single-buffer and batched kernels (each translation unit gets its own copy
+// of the constant table).
+//
+// Rounds (FIPS-197 Sec. 5.1) use the T-table form: output column c of a full
+// round is T0[s_c.b0] ^ T1[s_(c+1).b1] ^ T2[s_(c+2).b2] ^ T3[s_(c+3).b3] ^ rk,
+// i.e. SubBytes + ShiftRows + MixColumns + AddRoundKey in four lookups and
+// two 3-input XORs (v_bitop3_b32).  The last round (no MixColumns) picks the
+// S-box byte out of T0/T2 entries with v_perm_b32.
+//
+// Random table indices would serialise on LDS banks, so every lane reads its
+// own bank-resident copy.  The entry for index x sits at byte 256*x, and the
+// lane's copy at +4*k (k = lane mod COPIES): the address is built by one
+// v_perm_b32 that drops the state byte into bits 8..15 next to the lane's
+// constant bits.
+//   COPIES == 32: T0|T1 interleaved in [0, 64 KiB) (T1 at +128 B), T2|T3 in
+//                 [64 KiB, 128 KiB).  Lanes l and l+32 share a bank.
+//   COPIES == 64: T0 in [0, 64 KiB), T2 in [64 KiB, 128 KiB); T1 = rotl(T0, 8)
+//                 and T3 = rotl(T2, 8) are folded into one rotate per column.
+#pragma once
+
+#include "aes_tables.h"
+#include "aesctr_internal.h"
+
+namespace aesctr {
+namespace {
+
+
+__constant__ Tables c_tables = build_tables();
+
+constexpr int kLdsWords = 32768;   // 128 KiB
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Valid global memory for loads issued when a message has no whole block.
+__device__ u32x4 g_dummy_block;
+
+__device__ __forceinline__ uint32_t vperm(uint32_t s0, uint32_t s1, uint32_t sel)
+{
+    return __builtin_amdgcn_perm(s0, s1, sel);
+}
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint32_t rotl8(uint32_t x)
+{
+    return __builtin_amdgcn_alignbit(x, x, 24);
+}
+
+// Address of the entry for byte R of v in the table region selected by lb
+// (lb = 4*copy | region << 16): bytes [lb.b0, v.bR, lb.b2, 0].
+template <int R>
+__device__ __forceinline__ uint32_t taddr(uint32_t v, uint32_t lb)
+{
+    return vperm(v, lb, 0x0c020000u | ((4u + R) << 8));
+}
+
+__device__ __forceinline__ uint32_t lds_at(const char *lds, uint32_t byte_addr)
+{
+    return *reinterpret_cast<const uint32_t *>(lds + byte_addr);
+}
+
+// The LDS image is 8192 16-byte stores (128 KiB).  Thread t performs
+// stores w = t + u*WG, u < 8192/WG, each a 4-way broadcast of one table
+// entry.  The entries are read from the constant table first (fill_read) so
+// the caller can issue its own global loads before the table reads are
+// waited for; fill_write then stores them.
+constexpr int kFillStores = 8192;
+
+template <int WG>
+__device__ __forceinline__ void fill_read(uint32_t (&tv)[kFillStores / WG])
+{
+#pragma unroll
+    for (int u = 0; u < kFillStores / WG; ++u)
+        tv[u] = c_tables.t0[(threadIdx.x + u * WG) >> 5];
+}
+
+template <int COPIES, int WG>
+__device__ __forceinline__ void fill_write(uint32_t *lds, const uint32_t (&tv)[kFillStores / WG])
+{
+#pragma unroll
+    for (int u = 0; u < kFillStores / WG; ++u) {
+        const uint32_t w = threadIdx.x + u * WG;
+        const uint32_t i = w >> 5;
+        uint32_t val, addr;
+        if constexpr (COPIES == 32) {
+            const uint32_t q = w & 7, t = (w >> 3) & 3;
+            val = rotl32(tv[u], 8 * t);
+            addr = (t >> 1) * 65536 + i * 256 + (t & 1) * 128 + q * 16;
+        } else {
+            const uint32_t q = w & 15, t2 = (w >> 4) & 1;
+            val = t2 ? rotl32(tv[u], 16) : tv[u];
+            addr = t2 * 65536 + i * 256 + q * 16;
+        }
+        *reinterpret_cast<u32x4 *>(reinterpret_cast<char *>(lds) + addr) = u32x4{val, val, val, val};
+    }
+}
+
+template <int COPIES>
+struct TTable {
+    const char *lds;
+    uint32_t lb0, lb1;   // lane bits for region 0 / region 1
+
+    // T_t[byte R of v] for t = 0..3.
+    template <int T, int R>
+    __device__ __forceinline__ uint32_t get(uint32_t v) const
+    {
+        uint32_t a = taddr<R>(v, (T >= 2) ? lb1 : lb0);
+        if constexpr (COPIES == 32) {
+            return lds_at(lds, a + ((T & 1) ? 128u : 0u));
+        } else {
+            uint32_t e = lds_at(lds, a);
+            return (T & 1) ? rotl8(e) : e;
+        }
+    }
+
+    // Raw region entries (T0 or T2 region) without the odd-table rotation.
+    template <int REGION, int R>
+    __device__ __forceinline__ uint32_t raw(uint32_t v) const
+    {
+        return lds_at(lds, taddr<R>(v, REGION ? lb1 : lb0));
+    }
+
+    // One full round: s -> o with round key words k[0..3]; rk_rot holds
+    // rotr(k, 8) for the COPIES == 64 fold.
+    __device__ __forceinline__ void round(const uint32_t s[4], uint32_t o[4],
+                                          const uint32_t *k, const uint32_t *krot) const
+    {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t s0 = s[c], s1 = s[(c + 1) & 3], s2 = s[(c + 2) & 3], s3 = s[(c + 3) & 3];
+            if constexpr (COPIES == 32) {
+                o[c] = xor3(xor3(get<0, 0>(s0), get<1, 1>(s1), get<2, 2>(s2)), get<3, 3>(s3), k[c]);
+            } else {
+                // T1[b]^T3[d]^k = rotl8(T0[b]^T2[d]^rotr8(k))
+                uint32_t odd = rotl8(xor3(raw<0, 1>(s1), raw<1, 3>(s3), krot[c]));
+                o[c] = xor3(raw<0, 0>(s0), raw<1, 2>(s2), odd);
+            }
+        }
+    }
+
+    // Last round: S-box bytes only.  Row 0 byte from a T2 entry (S at byte 0),
+    // row 1 and row 2 from T0 entries (S at bytes 1, 2), row 3 from T2 (byte 3).
+    __device__ __forceinline__ void last_round(const uint32_t s[4], uint32_t o[4],
+                                               const uint32_t *k) const
+    {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t e0 = raw<1, 0>(s[c]);
+            uint32_t e1 = raw<0, 1>(s[(c + 1) & 3]);
+            uint32_t e2 = raw<0, 2>(s[(c + 2) & 3]);
+            uint32_t e3 = raw<1, 3>(s[(c + 3) & 3]);
+            uint32_t lo = vperm(e1, e0, 0x0c0c0500u);   // [e0.b0, e1.b1, 0, 0]
+            uint32_t hi = vperm(e3, e2, 0x07020c0cu);   // [0, 0, e2.b2, e3.b3]
+            o[c] = xor3(lo, hi, k[c]);
+        }
+    }
+};
+
+// Keystreams of N counter blocks, computed round by round across the N
+// blocks so their independent lookups interleave.  ctr[i] is already
+// ctr0 + j mod 2^32.
+template <int NR, int COPIES, int N>
+__device__ __forceinline__ void keystream(const TTable<COPIES> &tt, const CtrArgs &a,
+                                          const uint32_t *krot, const uint32_t *ctr, uint32_t (*ks)[4])
+{
+    uint32_t s[N][4], o[N][4];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        // Rounds 0 and 1 of the counter column; the other terms are in k1.
+        const uint32_t x = vperm(ctr[b], ctr[b], 0x00010203u) ^ a.x0;   // big-endian counter
+        s[b][0] = a.k1[0] ^ tt.template get<3, 3>(x);
+        s[b][1] = a.k1[1] ^ tt.template get<2, 2>(x);
+        s[b][2] = a.k1[2] ^ tt.template get<1, 1>(x);
+        s[b][3] = a.k1[3] ^ tt.template get<0, 0>(x);
+    }
+#pragma unroll
+    for (int r = 2; r < NR; ++r) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+            tt.round(s[b], o[b], &a.rk[4 * r], &krot[4 * r]);
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[b][c] = o[b][c];
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+        tt.last_round(s[b], ks[b], &a.rk[4 * NR]);
+}
+
+}  // namespace
+}  // namespace aesctr

@@ -1,0 +1,26 @@
+// tune.h -- launch shapes chosen by the autotuner, read from a JSON cache.
+//
+// The cache (written by the package's autotune module) is found through the
+// AESCTR_TUNE_CACHE environment variable, else as tune_cache.json beside the
+// shared library.  Format:
+//   {"entries": [{"variant": 1, "key_bits": 128, "size_log2": 23, "bpl": 2,
+//                 "wg": 1024, "grid_per_cu": 1, "copies": 64}, ...]}
+// A lookup takes the entry of the same variant and key size whose size_log2
+// is nearest to floor(log2(len)).
+#pragma once
+
+#include <stdint.h>
+
+namespace aesctr {
+
+struct TuneEntry {
+    int variant = 0, key_bits = 0, size_log2 = 0;
+    int bpl = 0, wg = 0, grid_per_cu = 0, copies = 0;
+};
+
+bool tune_lookup(int variant, int key_bits, uint64_t len, TuneEntry *out);
+
+// Batch-kernel shape from the same cache (entries with "variant": 10).
+bool tune_lookup_batch(TuneEntry *out);
+
+}  // namespace aesctr

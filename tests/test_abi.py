@@ -1,0 +1,99 @@
+"""Host-side checks of libaesctr.so that need no GPU.
+
+* the library loads and exports every function include/aesctr.h declares;
+* aes_expand_key (host code of the product, written independently of the
+  oracle) equals the oracle's FIPS-197 KeyExpansion;
+* argument validation returns the documented status before any device work.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2607_02630_amd as A
+from paper_2607_02630_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions() -> list[str]:
+    text = open(os.path.join(ROOT, "include", "aesctr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aes_\w+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = header_functions()
+    assert len(names) >= 14
+    L = ctypes.CDLL(N.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), f"{name} declared but not exported"
+    assert set(names) == set(N.SIGNATURES), "binding and header disagree"
+
+
+def test_strerror_names_every_status():
+    for code in range(0, -11, -1):
+        assert A.aes_strerror(code).startswith("AES_")
+    assert "unknown" in A.aes_strerror(-99)
+
+
+@pytest.mark.parametrize("klen", [16, 32])
+def test_expand_key_matches_oracle(klen):
+    g = np.random.default_rng(klen)
+    for _ in range(200):
+        key = g.bytes(klen)
+        s = A.aes_expand_key(key)
+        nr, w = oracle.expand(key)
+        assert s.nr == nr and s.key_bits == 8 * klen
+        assert list(s.rk[:4 * (nr + 1)]) == w
+
+
+def test_expand_key_rejects_bad_sizes():
+    for klen in (0, 15, 24, 31, 33):
+        with pytest.raises(A.AesError) as e:
+            A.aes_expand_key(bytes(klen))
+        assert e.value.status == N.AES_EINVAL
+    assert A.lib.aes_expand_key(None, 128, None) == N.AES_EINVAL
+
+
+def _crypt_rc(sched, nonce, ctr0, src, dst, n):
+    return A.lib.aes_ctr_crypt(ctypes.byref(sched) if sched is not None else None,
+                               nonce, ctr0, src, dst, n, None)
+
+
+def test_validation_before_device():
+    s = A.aes_expand_key(bytes(16))
+    nonce = bytes(12)
+    # len == 0 is a no-op, even with null buffers.
+    assert _crypt_rc(s, nonce, 1, None, None, 0) == N.AES_OK
+    assert _crypt_rc(None, nonce, 1, 0x1000, 0x2000, 16) == N.AES_EINVAL
+    assert _crypt_rc(s, None, 1, 0x1000, 0x2000, 16) == N.AES_EINVAL
+    assert _crypt_rc(s, nonce, 1, None, 0x2000, 16) == N.AES_EINVAL
+    assert _crypt_rc(s, nonce, 1, 0x1000, None, 16) == N.AES_EINVAL
+    # Partial overlap (in place is fine, checked on the GPU).
+    assert _crypt_rc(s, nonce, 1, 0x1000, 0x1008, 16) == N.AES_EOVERLAP
+    assert _crypt_rc(s, nonce, 1, 0x1008, 0x1000, 16) == N.AES_EOVERLAP
+    # More than 2^32 blocks.
+    assert _crypt_rc(s, nonce, 1, 0x1000, 0x10000000000000, (1 << 36) + 16) == N.AES_ERANGE
+    # A corrupted schedule.
+    bad = A.aes_expand_key(bytes(16))
+    bad.nr = 12
+    assert _crypt_rc(bad, nonce, 1, 0x1000, 0x2000, 16) == N.AES_EINVAL
+    bad = A.aes_expand_key(bytes(32))
+    bad.key_bits = 128
+    assert _crypt_rc(bad, nonce, 1, 0x1000, 0x2000, 16) == N.AES_EINVAL
+
+
+def test_launch_cfg_validation():
+    s = A.aes_expand_key(bytes(16))
+    for kw in (dict(variant=3), dict(blocks_per_lane=3), dict(wg_size=100), dict(wg_size=2048),
+               dict(grid=-1), dict(lds_copies=16)):
+        cfg = A.launch_cfg(**kw)
+        rc = A.lib.aes_ctr_crypt_cfg(ctypes.byref(s), bytes(12), 1, 0x1000, 0x2000, 16,
+                                     ctypes.byref(cfg), None)
+        assert rc == N.AES_EINVAL, kw
