@@ -42,8 +42,9 @@ def parse():
     ap.add_argument("--bits", type=int, default=128, choices=(128, 256))
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 T-table, 2 bitsliced")
     ap.add_argument("--sweep", action="store_true", help="also time 4 KiB..8 MiB + 256 MiB")
-    ap.add_argument("--batch", action="store_true", help="also time the 4096-request batch")
-    ap.add_argument("--serve", action="store_true", help="also run the serving loop")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4096-request batch leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-requests", type=int, default=100_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
@@ -244,12 +245,10 @@ def main():
 
     if args.sweep:
         result["sweep"] = run_sweep(torch, A, W, args)
-    if args.batch:
-        import bench_legs
-        result["batch"] = bench_legs.batch_leg(torch, A, W)
-    if args.serve:
-        import bench_legs
-        result["serving"] = bench_legs.serve_leg(torch, A, W)
+    if not args.no_batch:
+        result["batch"] = batch_leg(torch, A, W)
+    if not args.no_serve:
+        result["serving"] = serve_leg(torch, A, W, args.serve_requests)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(W, args.size, args.bits, args.cpu_seconds)
@@ -277,6 +276,165 @@ def run_sweep(torch, A, W, args):
                 log(f"sweep {bits} {'tt' if variant == 1 else 'bs'} {size}: {row}")
                 del ins, outs
                 torch.cuda.empty_cache()
+    return out
+
+
+def _median(xs):
+    xs = sorted(xs)
+    return xs[len(xs) // 2]
+
+
+def batch_leg(torch, A, W, reps=5):
+    """4096 requests, log-uniform 4 KiB..8 MiB, mixed AES-128/256 keys, own
+    nonce and counter each: one aes_ctr_crypt_batch (captured graph: upload
+    of the descriptor table + one persistent kernel) vs 4096 aes_ctr_crypt
+    launches (eager, graph-replayed) and vs synchronising after each."""
+    import numpy as np
+    import oracle
+    reqs = W.batch_requests()
+    offs, pos = [], 0
+    for r in reqs:
+        offs.append(pos)
+        pos += (r.length + 255) // 256 * 256
+    total = sum(r.length for r in reqs)
+    log(f"batch leg: {len(reqs)} requests, {total / 2**30:.2f} GiB")
+    src = W.device_payload(pos, 4242)
+    dst = torch.zeros_like(src)
+    t0 = time.perf_counter()
+    scheds = [A.aes_expand_key(r.key) for r in reqs]
+    expand_us = (time.perf_counter() - t0) / len(reqs) * 1e6
+    objs = [A.Request(s, r.nonce, r.ctr0, src.data_ptr() + o, dst.data_ptr() + o, r.length)
+            for s, r, o in zip(scheds, reqs, offs)]
+    arr = A.make_desc_array(objs)
+    st = torch.cuda.current_stream().cuda_stream
+    n = len(reqs)
+
+    def batched():
+        rc = A.lib.aes_ctr_crypt_batch(arr, n, st)
+        assert rc == 0, A.aes_strerror(rc)
+
+    for _ in range(2):
+        batched()
+    ms = []
+    for _ in range(reps):
+        with Timer(torch) as t:
+            batched()
+        ms.append(t.ms)
+    b_ms = _median(ms)
+    # Parity gate: first and last block of 256 sampled requests vs the oracle.
+    rng = np.random.default_rng(7)
+    for i in rng.choice(n, 256, replace=False):
+        r, o = reqs[i], offs[i]
+        nb = (r.length + 15) // 16
+        for j in (0, nb - 1):
+            a, b = o + 16 * j, min(o + 16 * j + 16, o + r.length)
+            ref = oracle.ctr(r.key, r.nonce, (r.ctr0 + j) & 0xFFFFFFFF, src[a:b].cpu().numpy())
+            if not np.array_equal(dst[a:b].cpu().numpy(), ref):
+                raise SystemExit(f"batch output differs from the oracle (request {i}, block {j})")
+
+    args = [(ctypes_byref(s), r.nonce, r.ctr0 & 0xFFFFFFFF, src.data_ptr() + o, dst.data_ptr() + o, r.length)
+            for s, r, o in zip(scheds, reqs, offs)]
+
+    def per_request(sync=False):
+        for a in args:
+            A.lib.aes_ctr_crypt(*a, st)
+            if sync:
+                torch.cuda.synchronize()
+
+    per_request()
+    ms = []
+    for _ in range(reps):
+        with Timer(torch) as t:
+            per_request()
+        ms.append(t.ms)
+    e_ms = _median(ms)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cst = torch.cuda.current_stream().cuda_stream
+        for a in args:
+            A.lib.aes_ctr_crypt(*a, cst)
+    g.replay()
+    ms = []
+    for _ in range(reps):
+        with Timer(torch) as t:
+            g.replay()
+        ms.append(t.ms)
+    gr_ms = _median(ms)
+    with Timer(torch) as t:
+        per_request(sync=True)
+    s_ms = t.ms
+    out = {"requests": n, "bytes": total, "key_bits": "2048 x 128 + 2048 x 256",
+           "batched_ms": round(b_ms, 3), "batched_gbps": round(total / b_ms / 1e6, 2),
+           "per_request_launch_ms": round(e_ms, 3), "per_request_launch_gbps": round(total / e_ms / 1e6, 2),
+           "per_request_graph_ms": round(gr_ms, 3), "per_request_graph_gbps": round(total / gr_ms / 1e6, 2),
+           "sync_per_request_ms": round(s_ms, 3), "sync_per_request_gbps": round(total / s_ms / 1e6, 2),
+           "speedup_vs_launches": round(e_ms / b_ms, 2), "speedup_vs_graph_launches": round(gr_ms / b_ms, 2),
+           "key_expansion_us_per_key": round(expand_us, 2), "parity_sampled_vs_oracle": True}
+    log(f"batch leg: {out}")
+    del g, src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def ctypes_byref(x):
+    import ctypes
+    return ctypes.byref(x)
+
+
+def serve_leg(torch, A, W, n_req=100_000, budget=4 << 30):
+    """Open-loop Poisson arrivals at 10/50/90% of the engine's measured
+    saturation rate on the serving mix (70% 64 KiB / 25% 1 MiB / 5% 8 MiB,
+    per-request AES-128 key, nonce, counter), device-resident payloads and a
+    4 GiB admission budget; latency from scheduled arrival to completion.
+    The synchronous per-request path (launch + synchronise, one at a time)
+    replays the same schedules."""
+    import numpy as np
+    from paper_2607_02630_amd import loadgen
+    g = np.random.default_rng(W.seed_for(5))
+    npool = 12000
+    which = g.choice(3, size=npool, p=W.SERVING_MIX)
+    lens = np.array(W.SERVING_SIZES, dtype=np.int64)[which]
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    total = int(lens.sum())
+    log(f"serving leg: pool of {npool} requests, {total / 2**30:.2f} GiB")
+    src = W.device_payload(total, 555)
+    dst = torch.zeros_like(src)
+    scheds = [A.aes_expand_key(g.bytes(16)) for _ in range(npool)]
+    objs = [A.Request(s, g.bytes(12), int(g.integers(0, 1 << 32)), src.data_ptr() + int(o),
+                      dst.data_ptr() + int(o), int(L)) for s, o, L in zip(scheds, offs, lens)]
+    pool = A.make_desc_array(objs)
+    out = {"budget_bytes": budget, "mix": "70% 64 KiB / 25% 1 MiB / 5% 8 MiB", "requests_per_point": n_req,
+           "payloads": "device-resident"}
+    with A.Engine(budget_bytes=budget, n_streams=2) as eng:
+        loadgen.run_engine(eng, pool, np.zeros(min(20000, n_req)))        # warm-up
+        sat = loadgen.run_engine(eng, pool, np.zeros(n_req))
+        out["saturation"] = {k: round(v, 3) for k, v in sat.items()}
+        rate = sat["achieved_rps"]
+        log(f"serving: saturation {rate:.0f} req/s, {sat['gbps']:.1f} GB/s")
+        points = []
+        for frac in (0.1, 0.5, 0.9):
+            arr = W.serving_trace(n_req, frac * rate)[0]
+            e = loadgen.run_engine(eng, pool, arr)
+            s = loadgen.run_sync(pool, arr[:min(n_req, 20000)], torch.cuda.current_stream().cuda_stream)
+            points.append({"offered_frac": frac, "offered_rps": round(frac * rate, 1),
+                           "engine": {k: round(v, 3) for k, v in e.items()},
+                           "sync_per_request": {k: round(v, 3) for k, v in s.items()}})
+            log(f"serving {frac:.0%}: engine p50 {e['p50_us']:.0f} p99 {e['p99_us']:.0f} us {e['gbps']:.1f} GB/s;"
+                f" sync p99 {s['p99_us']:.0f} us {s['gbps']:.1f} GB/s")
+        out["points"] = points
+        out["engine_stats"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in eng.stats().items()}
+    # Results are the same in the mix as alone: every pool entry's output.
+    torch.cuda.synchronize()
+    alone = torch.zeros_like(dst)
+    for o in objs:
+        A.aes_ctr_crypt(o.sched, o.nonce, o.ctr0, o.x, alone.data_ptr() + (o.out - dst.data_ptr()),
+                        length=o.length)
+    torch.cuda.synchronize()
+    out["same_alone_and_in_the_mix"] = bool(torch.equal(alone, dst))
+    if not out["same_alone_and_in_the_mix"]:
+        raise SystemExit("serving outputs differ from the single-request outputs")
+    del src, dst, alone
+    torch.cuda.empty_cache()
     return out
 
 

@@ -142,9 +142,11 @@ typedef struct {
  * index are staged in pinned host memory and copied by a node of a captured
  * HIP graph, replayed on each call.  Each request's output equals
  * aes_ctr_crypt on that request alone.  n == 0 is a no-op.
- * Errors: AES_EINVAL (null desc with n > 0, null sched, flags != 0, ...),
- * AES_ERANGE, AES_EOVERLAP (per request), AES_ENOMEM, AES_EDEVICE.
- * Thread-safe for calls on distinct streams. */
+ * Errors: AES_EINVAL (null desc with n > 0, null sched, flags != 0, a
+ * stream that is being captured -- the call launches its own graph and its
+ * staging is rewritten by later calls), AES_ERANGE, AES_EOVERLAP (per
+ * request), AES_ENOMEM, AES_EDEVICE.  Thread-safe for calls on distinct
+ * streams; calls on one stream are serialised. */
 int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream);
 
 /* Batch launch shape: tile_bytes (bytes of a request one wave-tile covers,
@@ -198,7 +200,7 @@ typedef struct {
     uint64_t budget_high_water;     /* max bytes admitted at once */
     uint64_t queued_now, inflight_now;
     double mean_batch_reqs;
-    double p50_us, p99_us, p999_us; /* submit -> completion observed by the poller */
+    double p50_us, p99_us, p999_us; /* arrival (submit) -> completion seen by the poller */
     double busy_s;                  /* wall time with at least one launch in flight */
 } aes_stats_t;
 
@@ -215,6 +217,13 @@ int aes_engine_destroy(aes_engine_t *e);
  * Errors: AES_EINVAL, AES_ERANGE, AES_EOVERLAP, AES_EAGAIN (larger than the
  * whole budget), AES_ECLOSED. */
 int aes_submit(aes_engine_t *e, const aes_ctr_desc_t *d, uint64_t *ticket);
+
+/* aes_submit with an explicit arrival time: t_arrival_ns on the
+ * CLOCK_MONOTONIC (steady) clock, the moment the request reached the server.
+ * Latency statistics then count from arrival rather than from the call, so a
+ * server that queued the request before submitting it (or a load generator
+ * running behind schedule) is charged for that wait. */
+int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t_arrival_ns, uint64_t *ticket);
 
 /* 1 = done (the ticket is retired by this call), 0 = pending, < 0 = error
  * (AES_ENOTFOUND, AES_EDEVICE if the request's launch failed, AES_ECANCELED).

@@ -88,6 +88,8 @@ SIGNATURES = {
     "aes_engine_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "aes_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aes_ctr_desc_t),
                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "aes_submit_at": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aes_ctr_desc_t), ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_uint64)]),
     "aes_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "aes_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64]),
     "aes_engine_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aes_stats_t)]),

@@ -1,0 +1,161 @@
+"""Autotuner for the launch shapes (writes tune_cache.json beside the library).
+
+For each kernel variant, key size and message size of the sweep workloads
+(4 KiB .. 8 MiB and 256 MiB), every candidate shape is run on the workload's
+seeded input and its output digest is compared with the stored digest the
+oracle wrote (tests/golden/ctr_digests.json) -- a candidate that is not
+bit-exact is discarded -- then timed as K launches replayed from a captured
+graph over buffers larger than the Infinity Cache.  The fastest shape per
+(variant, key size, size) is written to the cache, which libaesctr.so reads
+(AESCTR_TUNE_CACHE or tune_cache.json next to the library).  The batch
+kernel's tile size and blocks per lane are tuned on the 4096-request batch.
+
+Usage: python -m paper_2607_02630_amd.autotune [--quick] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import itertools
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+MiB = 1 << 20
+
+
+def _golden():
+    with open(os.path.join(ROOT, "tests", "golden", "ctr_digests.json")) as f:
+        return json.load(f)["sweep"]
+
+
+def candidates(variant: int, quick: bool):
+    if variant == 1:
+        for c, b, w in itertools.product((32, 64), (1, 2, 4), (512, 1024) if quick else (256, 512, 1024)):
+            yield dict(variant=1, lds_copies=c, blocks_per_lane=b, wg_size=w, grid=0)
+    else:
+        for w, gm in itertools.product((64, 128, 256), (1, 2, 4)):
+            yield dict(variant=2, wg_size=w, grid=gm)
+
+
+def time_shape(torch, A, sched, nonce, ins, outs, cfg, steps):
+    n = len(ins)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(steps):
+            A.aes_ctr_crypt(sched, nonce, 1, ins[i % n], outs[i % n], cfg=cfg)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="fewer sizes and shapes")
+    ap.add_argument("--out", default=os.path.join(HERE, "tune_cache.json"))
+    args = ap.parse_args(argv)
+    sys.path.insert(0, ROOT)
+    import torch
+    import workloads as W
+    import paper_2607_02630_amd as A
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    gold = _golden()
+    sizes = [64 * 1024, MiB, 8 * MiB, W.BIG_SIZE] if args.quick else W.SWEEP_SIZES + [W.BIG_SIZE]
+    entries, report = [], []
+    for bits in (128, 256):
+        key, nonce = W.sweep_key(bits)
+        sched = A.aes_expand_key(key)
+        for size in sizes:
+            payload = W.sweep_payload(size, bits)
+            nbuf = max(2, math.ceil(768 * MiB / (2 * size)))
+            src = torch.from_numpy(payload).cuda()
+            ins = [src.clone() for _ in range(nbuf)]
+            outs = [torch.empty_like(src) for _ in range(nbuf)]
+            steps = max(10, min(500, int(2e9 / size)))
+            for variant in (1, 2):
+                best = None
+                for kw in candidates(variant, args.quick):
+                    grid = kw.pop("grid")
+                    cfg = A.launch_cfg(grid=grid * cus if variant == 2 else 0, **kw)
+                    A.aes_ctr_crypt(sched, nonce, 1, ins[0], outs[0], cfg=cfg)
+                    torch.cuda.synchronize()
+                    digest = hashlib.sha256(outs[0].cpu().numpy().tobytes()).hexdigest()
+                    if digest != gold[f"{bits}/{size}"]:
+                        raise SystemExit(f"candidate {kw} is not bit-exact at AES-{bits} {size} B")
+                    ms = time_shape(torch, A, sched, nonce, ins, outs, cfg, steps)
+                    kw["grid"] = grid
+                    if best is None or ms < best[0]:
+                        best = (ms, kw)
+                ms, kw = best
+                entry = {"variant": variant, "key_bits": bits, "size_log2": int(math.log2(size)),
+                         "bpl": kw.get("blocks_per_lane", 1), "wg": kw["wg_size"],
+                         "grid_per_cu": kw["grid"] if variant == 2 else 1,
+                         "copies": kw.get("lds_copies", 0)}
+                entries.append(entry)
+                report.append({**entry, "us": round(ms * 1e3, 3), "gbps": round(size / ms / 1e6, 1)})
+                print(json.dumps(report[-1]), flush=True)
+            del ins, outs, src
+            torch.cuda.empty_cache()
+    entries.append(tune_batch(torch, A, W, cus))
+    with open(args.out, "w") as f:
+        json.dump({"generated": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries,
+                   "measured": report}, f, indent=1)
+        f.write("\n")
+    print(f"wrote {args.out}")
+
+
+def tune_batch(torch, A, W, cus):
+    """Tile size and blocks per lane of the batch kernel on the 4096-request
+    batch; each candidate must reproduce the first candidate's output."""
+    reqs = W.batch_requests()
+    offs, pos = [], 0
+    for r in reqs:
+        offs.append(pos)
+        pos += (r.length + 255) // 256 * 256
+    src = W.device_payload(pos, 4242)
+    dst = torch.zeros_like(src)
+    scheds = [A.aes_expand_key(r.key) for r in reqs]
+    objs = [A.Request(s, r.nonce, r.ctr0, src.data_ptr() + o, dst.data_ptr() + o, r.length)
+            for s, r, o in zip(scheds, reqs, offs)]
+    arr = A.make_desc_array(objs)
+    ref = None
+    best = None
+    for tile, bpl in itertools.product((4096, 16384, 65536), (1, 2)):
+        cfg = A.batch_cfg(tile_bytes=tile, blocks_per_lane=bpl)
+        dst.zero_()
+        A.aes_ctr_crypt_batch(objs, cfg=cfg, descs=arr)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = dst.clone()
+        elif not torch.equal(ref, dst):
+            raise SystemExit(f"batch candidate tile={tile} bpl={bpl} changed the output")
+        times = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            A.aes_ctr_crypt_batch(objs, cfg=cfg, descs=arr)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = sorted(times)[1]
+        print(json.dumps({"batch_tile_bytes": tile, "bpl": bpl, "ms": round(ms, 3)}), flush=True)
+        if best is None or ms < best[0]:
+            best = (ms, tile, bpl)
+    del src, dst, ref
+    torch.cuda.empty_cache()
+    return {"variant": 10, "key_bits": 0, "size_log2": 0, "bpl": best[2], "wg": 1024, "grid_per_cu": 1,
+            "copies": 0, "tile_bytes": best[1]}
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,15 @@ static_assert(sizeof(BatchDesc) == 320, "descriptor layout");
 
 int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream_t st);
 
+// Host side of the batch path (batch.cpp).  make_batch_record expands one
+// validated request into its device record; launch_records stages up to any
+// number of records (kMaxBatch per launch) on the (device, stream) context and
+// launches them, through the per-slot captured graph or a plain copy+launch.
+int check_desc(const aes_ctr_desc_t &d);
+void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o);
+int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
+                   int bpl, bool use_graph);
+
 // Defaults before tuning, per variant and size.
 Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &di);
 

@@ -136,30 +136,20 @@ int build_graph(BatchCtx *c, int s, int grid, int bpl)
     return AES_OK;
 }
 
-// Fill staging slot `buf` with requests [first, first + n) and return the
-// number of bytes to upload.
-size_t stage(uint8_t *buf, const aes_ctr_desc_t *d, size_t n, uint32_t tile_blocks)
+// Copy n prebuilt records into staging slot `buf`, assigning first tiles.
+// Returns the bytes to upload, or 0 if the tile count would overflow.
+size_t stage(uint8_t *buf, const BatchDesc *recs, size_t n, uint32_t tile_blocks)
 {
     BatchHeader *h = reinterpret_cast<BatchHeader *>(buf);
     BatchDesc *out = reinterpret_cast<BatchDesc *>(buf + sizeof(BatchHeader));
     uint64_t tiles = 0;
     for (size_t i = 0; i < n; ++i) {
-        KeyMaterial km;
-        make_key_material(*d[i].sched, d[i].nonce, &km);
-        BatchDesc &o = out[i];
-        o.in = reinterpret_cast<uint64_t>(d[i].in);
-        o.out = reinterpret_cast<uint64_t>(d[i].out);
-        o.len = d[i].len;
-        o.ctr0 = d[i].ctr0;
-        o.x0 = km.x0;
-        o.nr = static_cast<uint32_t>(km.nr);
-        o.aligned = ((o.in | o.out) & 15) == 0;
-        memcpy(o.k1, km.k1, sizeof(o.k1));
-        o.tile0 = static_cast<uint32_t>(tiles);
-        memset(o.pad, 0, sizeof(o.pad));
-        memcpy(o.rk, km.rk, sizeof(o.rk));
-        const uint64_t blocks = (d[i].len + 15) / 16;
+        out[i] = recs[i];
+        out[i].tile0 = static_cast<uint32_t>(tiles);
+        const uint64_t blocks = (recs[i].len + 15) / 16;
         tiles += (blocks + tile_blocks - 1) / tile_blocks;
+        if (tiles > 0x7fffffffu)
+            return 0;
     }
     memset(h, 0, sizeof(*h));
     h->n = static_cast<uint32_t>(n);
@@ -170,6 +160,81 @@ size_t stage(uint8_t *buf, const aes_ctr_desc_t *d, size_t n, uint32_t tile_bloc
 }
 
 }  // namespace
+
+void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o)
+{
+    KeyMaterial km;
+    make_key_material(*d.sched, d.nonce, &km);
+    memset(o, 0, sizeof(*o));
+    o->in = reinterpret_cast<uint64_t>(d.in);
+    o->out = reinterpret_cast<uint64_t>(d.out);
+    o->len = d.len;
+    o->ctr0 = d.ctr0;
+    o->x0 = km.x0;
+    o->nr = static_cast<uint32_t>(km.nr);
+    o->aligned = ((o->in | o->out) & 15) == 0;
+    memcpy(o->k1, km.k1, sizeof(o->k1));
+    memcpy(o->rk, km.rk, sizeof(o->rk));
+}
+
+int check_desc(const aes_ctr_desc_t &d)
+{
+    int rc = check_sched(d.sched);
+    if (rc != AES_OK)
+        return rc;
+    if (d.flags != 0)
+        return AES_EINVAL;
+    return check_buffers(d.in, d.out, d.len);
+}
+
+int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
+                   int bpl, bool use_graph)
+{
+    int rc;
+    BatchCtx *c = get_ctx(device, st, &rc);
+    if (!c)
+        return rc;
+    const uint32_t tile_blocks = static_cast<uint32_t>(tile_bytes / 16);
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (size_t first = 0; first < n; first += kMaxBatch) {
+        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
+        const int slot = c->next_slot;
+        c->next_slot = (c->next_slot + 1) % kSlots;
+        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
+            (void)hipGetLastError();
+            return AES_EDEVICE;
+        }
+        const size_t bytes = stage(c->staging[slot], recs + first, m, tile_blocks);
+        if (bytes == 0)
+            return AES_ERANGE;
+        if (use_graph) {
+            SlotGraph &sg = c->g[slot];
+            if (!sg.exec || sg.grid != grid || sg.bpl != bpl) {
+                if ((rc = build_graph(c, slot, grid, bpl)) != AES_OK)
+                    return rc;
+            }
+            if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
+                                                  hipMemcpyHostToDevice) != hipSuccess ||
+                hipGraphLaunch(sg.exec, st) != hipSuccess) {
+                (void)hipGetLastError();
+                return AES_EDEVICE;
+            }
+        } else {
+            if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+                (void)hipGetLastError();
+                return AES_EDEVICE;
+            }
+            if ((rc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, st)) != AES_OK)
+                return rc;
+        }
+        if (hipEventRecord(c->done[slot], st) != hipSuccess) {
+            (void)hipGetLastError();
+            return AES_EDEVICE;
+        }
+        c->used[slot] = true;
+    }
+    return AES_OK;
+}
 
 }  // namespace aesctr
 
@@ -183,21 +248,16 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
     if (!desc)
         return AES_EINVAL;
     for (size_t i = 0; i < n; ++i) {
-        int rc = check_sched(desc[i].sched);
+        int rc = check_desc(desc[i]);
         if (rc != AES_OK)
-            return rc;
-        if (desc[i].flags != 0)
-            return AES_EINVAL;
-        if ((rc = check_buffers(desc[i].in, desc[i].out, desc[i].len)) != AES_OK)
             return rc;
     }
     BatchShape sh{16384, 1024, 0, 1, 1};
     TuneEntry te;
     if (tune_lookup_batch(&te)) {
-        sh.bpl = te.bpl;
-        sh.grid = 0;
-        if (te.copies > 0)   // the batch entry stores tile bytes in `copies`
-            sh.tile_bytes = te.copies;
+        sh.bpl = te.bpl <= 2 ? te.bpl : 1;
+        if (te.tile_bytes >= 1024 && te.tile_bytes % 1024 == 0)
+            sh.tile_bytes = te.tile_bytes;
     }
     if (cfg) {
         if (cfg->tile_bytes < 0 || (cfg->tile_bytes && (cfg->tile_bytes % 1024 != 0 || cfg->tile_bytes > (1 << 26))))
@@ -217,7 +277,6 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
         return rc;
     if (sh.grid == 0)
         sh.grid = di.num_cus;
-    const uint32_t tile_blocks = static_cast<uint32_t>(sh.tile_bytes / 16);
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -228,46 +287,11 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
     if (cs != hipStreamCaptureStatusNone)
         return AES_EINVAL;
 
-    BatchCtx *c = get_ctx(di.ordinal, stream, &rc);
-    if (!c)
-        return rc;
-    std::lock_guard<std::mutex> lk(c->mu);
-    for (size_t first = 0; first < n; first += kMaxBatch) {
-        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
-        const int slot = c->next_slot;
-        c->next_slot = (c->next_slot + 1) % kSlots;
-        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
-            (void)hipGetLastError();
-            return AES_EDEVICE;
-        }
-        const size_t bytes = stage(c->staging[slot], desc + first, m, tile_blocks);
-        if (sh.use_graph) {
-            SlotGraph &sg = c->g[slot];
-            if (!sg.exec || sg.grid != sh.grid || sg.bpl != sh.bpl) {
-                if ((rc = build_graph(c, slot, sh.grid, sh.bpl)) != AES_OK)
-                    return rc;
-            }
-            if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
-                                                  hipMemcpyHostToDevice) != hipSuccess ||
-                hipGraphLaunch(sg.exec, st) != hipSuccess) {
-                (void)hipGetLastError();
-                return AES_EDEVICE;
-            }
-        } else {
-            if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
-                (void)hipGetLastError();
-                return AES_EDEVICE;
-            }
-            if ((rc = launch_ctr_batch(c->dev_table, sh.grid, 1024, sh.bpl, st)) != AES_OK)
-                return rc;
-        }
-        if (hipEventRecord(c->done[slot], st) != hipSuccess) {
-            (void)hipGetLastError();
-            return AES_EDEVICE;
-        }
-        c->used[slot] = true;
-    }
-    return AES_OK;
+    thread_local std::vector<BatchDesc> recs;
+    recs.resize(n);
+    for (size_t i = 0; i < n; ++i)
+        make_batch_record(desc[i], &recs[i]);
+    return launch_records(di.ordinal, st, recs.data(), n, sh.tile_bytes, sh.grid, sh.bpl, sh.use_graph != 0);
 }
 
 extern "C" int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream)

@@ -1,13 +1,332 @@
-// engine.cpp -- placeholder until the engine lands.
-#include "aesctr_internal.h"
+// engine.cpp -- the serving engine: submit / poll / wait over continuous
+// batching on HIP streams.
+//
+// One driver thread per engine owns the device side.  In a loop it
+//   1. polls the event behind each stream's in-flight launch (the paper's
+//      completion test by event query, Sec. 6 setup) and retires finished
+//      launches, releasing their bytes from the budget;
+//   2. for every stream with nothing in flight, takes everything admitted so
+//      far (FIFO, within the byte budget and per-launch limits) and launches
+//      it as one persistent batch kernel -- requests that arrived while other
+//      launches were running join the next one, and launches on different
+//      streams overlap on the device;
+//   3. sleeps when there is nothing queued and nothing in flight.
+// Request records (pointers, counter parameters, expanded key material) are
+// built on the submitting thread, so the driver only copies them into the
+// launch's descriptor table.
+//
+// With host_buffers the request buffers are pinned host memory (hipHostMalloc)
+// that the kernel reads and writes directly over PCIe; otherwise they are
+// device memory.
+#include <atomic>
+#include <errno.h>
+#include <sys/eventfd.h>
+#include <thread>
+#include <unistd.h>
+#include <vector>
 
-extern "C" {
-int aes_engine_create(const aes_engine_cfg_t *, aes_engine_t **) { return AES_EDEVICE; }
-int aes_engine_destroy(aes_engine_t *) { return AES_EINVAL; }
-int aes_submit(aes_engine_t *, const aes_ctr_desc_t *, uint64_t *) { return AES_EINVAL; }
-int aes_poll(aes_engine_t *, uint64_t) { return AES_EINVAL; }
-int aes_wait(aes_engine_t *, uint64_t, int64_t) { return AES_EINVAL; }
-int aes_engine_stats(aes_engine_t *, aes_stats_t *) { return AES_EINVAL; }
-int aes_engine_reset_stats(aes_engine_t *) { return AES_EINVAL; }
-int aes_engine_completion_fd(aes_engine_t *) { return AES_EINVAL; }
+#include "aesctr_internal.h"
+#include "engine_core.h"
+
+using aesctr::BatchDesc;
+using Core = aesctr::EngineCore<BatchDesc>;
+using Req = Core::Req;
+
+struct aes_engine {
+    aes_engine(uint64_t budget, size_t max_reqs, uint64_t max_bytes) : core(budget, max_reqs, max_bytes) {}
+
+    Core core;
+    int device = 0;
+    int num_cus = 0;
+    int tile_bytes = 16384;
+    int host_buffers = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<std::vector<Req>> inflight;
+    std::vector<int64_t> launched_ns;
+    std::thread driver;
+    int efd = -1;
+};
+
+namespace {
+
+constexpr int kMaxStreams = 16;
+
+void notify_fd(int fd)
+{
+    if (fd >= 0) {
+        uint64_t one = 1;
+        ssize_t r = write(fd, &one, sizeof(one));
+        (void)r;   // EAGAIN only when the counter is saturated: still readable
+    }
+}
+
+int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vector<BatchDesc> &recs)
+{
+    recs.resize(batch.size());
+    uint64_t tiles = 0;
+    const uint64_t tile_blocks = static_cast<uint64_t>(e->tile_bytes / 16);
+    for (size_t i = 0; i < batch.size(); ++i) {
+        recs[i] = batch[i].rec;
+        tiles += ((batch[i].rec.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
+    }
+    // Sixteen waves per workgroup each claim tiles; no more workgroups than
+    // can find work.
+    uint64_t grid = (tiles + 15) / 16;
+    if (grid < 1)
+        grid = 1;
+    if (grid > static_cast<uint64_t>(e->num_cus))
+        grid = e->num_cus;
+    int rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), e->tile_bytes,
+                                    static_cast<int>(grid), 1, false);
+    if (rc != AES_OK)
+        return rc;
+    if (hipEventRecord(e->events[s], e->streams[s]) != hipSuccess) {
+        (void)hipGetLastError();
+        return AES_EDEVICE;
+    }
+    return AES_OK;
+}
+
+void drive(aes_engine *e)
+{
+    if (hipSetDevice(e->device) != hipSuccess) {
+        (void)hipGetLastError();
+        e->core.close();
+        e->core.cancel_queued(AES_EDEVICE);
+        return;
+    }
+    const int ns = static_cast<int>(e->streams.size());
+    std::vector<Req> batch;
+    std::vector<BatchDesc> recs;
+    int active = 0;
+    int64_t busy_since = 0;
+    for (;;) {
+        bool progressed = false;
+        for (int s = 0; s < ns; ++s) {
+            if (e->inflight[s].empty())
+                continue;
+            hipError_t q = hipEventQuery(e->events[s]);
+            if (q == hipErrorNotReady)
+                continue;
+            const int status = q == hipSuccess ? AES_OK : AES_EDEVICE;
+            if (q != hipSuccess)
+                (void)hipGetLastError();
+            const int64_t now = Core::now_ns();
+            e->core.complete(e->inflight[s], status, now);
+            e->inflight[s].clear();
+            if (--active == 0)
+                e->core.add_busy(now - busy_since);
+            progressed = true;
+        }
+        for (int s = 0; s < ns; ++s) {
+            if (!e->inflight[s].empty())
+                continue;
+            if (!e->core.take_batch(batch))
+                break;
+            int rc = launch_batch(e, s, batch, recs);
+            if (rc != AES_OK) {
+                e->core.complete(batch, rc, Core::now_ns());
+                continue;
+            }
+            if (active++ == 0)
+                busy_since = Core::now_ns();
+            e->inflight[s].swap(batch);
+            progressed = true;
+        }
+        if (!progressed) {
+            if (active > 0) {
+                std::this_thread::yield();
+            } else {
+                if (e->core.closing_and_drained())
+                    break;
+                e->core.wait_for_work(2000000);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int aes_engine_create(const aes_engine_cfg_t *cfg, aes_engine_t **out)
+{
+    if (!out)
+        return AES_EINVAL;
+    *out = nullptr;
+    aes_engine_cfg_t c{};
+    if (cfg)
+        c = *cfg;
+    const uint64_t budget = c.budget_bytes ? c.budget_bytes : (4ull << 30);
+    const int nstreams = c.n_streams ? c.n_streams : 2;
+    const int max_reqs = c.max_batch_reqs ? c.max_batch_reqs : aesctr::kMaxBatch;
+    const uint64_t max_bytes = c.max_batch_bytes ? c.max_batch_bytes : budget;
+    if (nstreams < 1 || nstreams > kMaxStreams || max_reqs < 1 || c.key_slots < 0 ||
+        (c.host_buffers != 0 && c.host_buffers != 1))
+        return AES_EINVAL;
+
+    int dev = c.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return AES_EDEVICE;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) {
+        (void)hipGetLastError();
+        return AES_EDEVICE;
+    }
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return AES_EDEVICE;
+    }
+    aesctr::DeviceInfo di;
+    int rc = aesctr::device_info(&di);
+    if (rc != AES_OK) {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+        return rc;
+    }
+
+    aes_engine *e = new aes_engine(budget, static_cast<size_t>(max_reqs), max_bytes);
+    e->device = dev;
+    e->num_cus = di.num_cus;
+    e->host_buffers = c.host_buffers;
+    e->inflight.resize(nstreams);
+    for (int s = 0; s < nstreams; ++s) {
+        hipStream_t st;
+        hipEvent_t ev;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            rc = AES_EDEVICE;
+            break;
+        }
+        e->streams.push_back(st);
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            rc = AES_EDEVICE;
+            break;
+        }
+        e->events.push_back(ev);
+    }
+    if (prev >= 0)
+        (void)hipSetDevice(prev);
+    if (rc != AES_OK) {
+        (void)hipGetLastError();
+        for (hipStream_t st : e->streams)
+            (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : e->events)
+            (void)hipEventDestroy(ev);
+        delete e;
+        return rc;
+    }
+    e->efd = eventfd(0, EFD_NONBLOCK | EFD_CLOEXEC);
+    const int fd = e->efd;
+    e->core.set_on_complete([fd] { notify_fd(fd); });
+    e->driver = std::thread(drive, e);
+    *out = e;
+    return AES_OK;
+}
+
+extern "C" int aes_engine_destroy(aes_engine_t *e)
+{
+    if (!e)
+        return AES_EINVAL;
+    e->core.close();
+    if (e->driver.joinable())
+        e->driver.join();
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(e->device);
+    for (hipStream_t st : e->streams)
+        (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : e->events)
+        (void)hipEventDestroy(ev);
+    if (prev >= 0)
+        (void)hipSetDevice(prev);
+    if (e->efd >= 0)
+        close(e->efd);
+    delete e;
+    return AES_OK;
+}
+
+namespace {
+
+// Device address of pinned host memory; AES_EINVAL if p is not memory the
+// device can reach (e.g. pageable host memory).
+int host_to_device(const void *p, uint64_t *dev)
+{
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return AES_EINVAL;
+    }
+    if (at.type != hipMemoryTypeHost || !at.devicePointer)
+        return AES_EINVAL;
+    *dev = reinterpret_cast<uint64_t>(at.devicePointer);
+    return AES_OK;
+}
+
+}  // namespace
+
+extern "C" int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t_arrival_ns, uint64_t *ticket)
+{
+    if (!e || !d || !ticket || t_arrival_ns < 0)
+        return AES_EINVAL;
+    int rc = aesctr::check_desc(*d);
+    if (rc != AES_OK)
+        return rc;
+    Req r;
+    r.bytes = d->len;
+    aesctr::make_batch_record(*d, &r.rec);
+    if (e->host_buffers && d->len > 0) {
+        // The kernel reads and writes the pinned host buffers directly.
+        uint64_t din = 0, dout = 0;
+        if ((rc = host_to_device(d->in, &din)) != AES_OK || (rc = host_to_device(d->out, &dout)) != AES_OK)
+            return rc;
+        r.rec.in = din;
+        r.rec.out = dout;
+        r.rec.aligned = ((din | dout) & 15) == 0;
+    }
+    return e->core.submit(std::move(r), ticket, t_arrival_ns);
+}
+
+extern "C" int aes_submit(aes_engine_t *e, const aes_ctr_desc_t *d, uint64_t *ticket)
+{
+    return aes_submit_at(e, d, e ? Core::now_ns() : 0, ticket);
+}
+
+extern "C" int aes_poll(aes_engine_t *e, uint64_t ticket)
+{
+    if (!e)
+        return AES_EINVAL;
+    return e->core.poll(ticket);
+}
+
+extern "C" int aes_wait(aes_engine_t *e, uint64_t ticket, int64_t timeout_us)
+{
+    if (!e)
+        return AES_EINVAL;
+    return e->core.wait(ticket, timeout_us);
+}
+
+extern "C" int aes_engine_stats(aes_engine_t *e, aes_stats_t *out)
+{
+    if (!e || !out)
+        return AES_EINVAL;
+    e->core.stats(out);
+    return AES_OK;
+}
+
+extern "C" int aes_engine_reset_stats(aes_engine_t *e)
+{
+    if (!e)
+        return AES_EINVAL;
+    e->core.reset_stats();
+    return AES_OK;
+}
+
+extern "C" int aes_engine_completion_fd(aes_engine_t *e)
+{
+    if (!e)
+        return AES_EINVAL;
+    return e->efd >= 0 ? e->efd : AES_EDEVICE;
 }

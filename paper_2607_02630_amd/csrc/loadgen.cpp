@@ -1,0 +1,147 @@
+// loadgen.cpp -- open-loop load generation against the serving engine and
+// against the synchronous per-request path (see include/aesloadgen.h).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <hip/hip_runtime.h>
+#include <thread>
+#include <vector>
+
+#include "../../include/aesloadgen.h"
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+void spin_until(int64_t t)
+{
+    while (now_ns() < t) {
+    }
+}
+
+void fill_percentiles(std::vector<double> &lat, aes_load_result_t *o)
+{
+    if (lat.empty())
+        return;
+    std::sort(lat.begin(), lat.end());
+    auto pct = [&](double p) {
+        size_t i = static_cast<size_t>(p * (lat.size() - 1) + 0.5);
+        return lat[std::min(i, lat.size() - 1)];
+    };
+    o->p50_us = pct(0.50);
+    o->p99_us = pct(0.99);
+    o->p999_us = pct(0.999);
+    o->max_us = lat.back();
+}
+
+}  // namespace
+
+extern "C" int aes_load_engine(aes_engine_t *e, const aes_ctr_desc_t *pool, size_t npool, const double *arrival_s,
+                               size_t n, aes_load_result_t *out)
+{
+    if (!e || !pool || !npool || (!arrival_s && n) || !out)
+        return AES_EINVAL;
+    *out = aes_load_result_t{};
+    aes_engine_reset_stats(e);
+    std::vector<uint64_t> tickets(n);
+    std::atomic<size_t> submitted{0};
+    std::atomic<bool> stop{false};
+    int first_err = AES_OK;
+    uint64_t bytes = 0;
+    const int64_t t0 = now_ns() + 2000000;   // start 2 ms from now
+    int64_t last_done = t0;
+    uint64_t errors = 0;
+
+    // Retire tickets in submission order on a second thread, so the submitter
+    // never blocks; the engine itself timestamps each completion.
+    std::thread collector([&] {
+        size_t i = 0;
+        for (;;) {
+            const size_t avail = submitted.load(std::memory_order_acquire);
+            if (i < avail) {
+                int rc = aes_wait(e, tickets[i], -1);
+                if (rc != AES_OK)
+                    ++errors;
+                last_done = now_ns();
+                ++i;
+            } else if (stop.load(std::memory_order_acquire) && i >= submitted.load()) {
+                break;
+            } else {
+                std::this_thread::yield();
+            }
+        }
+    });
+    double max_lag = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const int64_t t = t0 + static_cast<int64_t>(arrival_s[i] * 1e9);
+        spin_until(t);
+        max_lag = std::max(max_lag, (now_ns() - t) * 1e-3);
+        const aes_ctr_desc_t &d = pool[i % npool];
+        int rc = aes_submit_at(e, &d, t, &tickets[i]);
+        if (rc != AES_OK) {
+            first_err = rc;
+            break;
+        }
+        bytes += d.len;
+        submitted.store(i + 1, std::memory_order_release);
+    }
+    stop.store(true, std::memory_order_release);
+    collector.join();
+
+    aes_stats_t st;
+    aes_engine_stats(e, &st);
+    out->wall_s = (last_done - t0) * 1e-9;
+    out->completed = st.completed;
+    out->errors = errors;
+    out->achieved_rps = out->wall_s > 0 ? st.completed / out->wall_s : 0;
+    out->gbps = out->wall_s > 0 ? bytes / out->wall_s / 1e9 : 0;
+    out->max_lag_us = max_lag;
+    out->p50_us = st.p50_us;
+    out->p99_us = st.p99_us;
+    out->p999_us = st.p999_us;
+    out->max_us = 0;
+    return first_err;
+}
+
+extern "C" int aes_load_sync(const aes_ctr_desc_t *pool, size_t npool, const double *arrival_s, size_t n,
+                             void *stream, aes_load_result_t *out)
+{
+    if (!pool || !npool || (!arrival_s && n) || !out)
+        return AES_EINVAL;
+    *out = aes_load_result_t{};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<double> lat;
+    lat.reserve(n);
+    uint64_t bytes = 0;
+    double max_lag = 0;
+    const int64_t t0 = now_ns() + 2000000;
+    int64_t last = t0;
+    for (size_t i = 0; i < n; ++i) {
+        const int64_t t = t0 + static_cast<int64_t>(arrival_s[i] * 1e9);
+        spin_until(t);    // no-op once the server has fallen behind
+        max_lag = std::max(max_lag, (now_ns() - t) * 1e-3);
+        const aes_ctr_desc_t &d = pool[i % npool];
+        int rc = aes_ctr_crypt(d.sched, d.nonce, d.ctr0, d.in, d.out, d.len, stream);
+        if (rc != AES_OK)
+            return rc;
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            return AES_EDEVICE;
+        }
+        last = now_ns();
+        lat.push_back((last - t) * 1e-3);
+        bytes += d.len;
+    }
+    out->wall_s = (last - t0) * 1e-9;
+    out->completed = n;
+    out->achieved_rps = out->wall_s > 0 ? n / out->wall_s : 0;
+    out->gbps = out->wall_s > 0 ? bytes / out->wall_s / 1e9 : 0;
+    out->max_lag_us = max_lag;
+    fill_percentiles(lat, out);
+    return AES_OK;
+}

@@ -1,0 +1,142 @@
+// Host-logic test of the serving engine's scheduling core (no GPU, no AES):
+// a stand-in driver thread takes batches and completes them after a short
+// delay, while several submitter threads push requests of mixed sizes.
+// Checks: the byte budget is never exceeded, admission is FIFO, every ticket
+// completes exactly once, poll/wait semantics, oversize rejection, shutdown.
+// Built with g++ -fsanitize=thread by tests/test_engine_core.py.
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "../../paper_2607_02630_amd/csrc/engine_core.h"
+
+using namespace aesctr;
+struct Rec {
+    uint64_t tag;
+};
+using Core = EngineCore<Rec>;
+
+#define CHECK(c)                                                                  \
+    do {                                                                          \
+        if (!(c)) {                                                               \
+            std::fprintf(stderr, "CHECK failed: %s (line %d)\n", #c, __LINE__);   \
+            std::exit(1);                                                         \
+        }                                                                         \
+    } while (0)
+
+int main()
+{
+    const uint64_t budget = 64 << 20;
+    Core core(budget, 256, budget);
+    std::atomic<uint64_t> inflight{0}, max_inflight{0};
+    std::atomic<bool> stop{false};
+    std::atomic<uint64_t> last_taken{0};
+    std::atomic<int> order_violations{0};
+
+    // Stand-in driver: up to two batches in flight, each "runs" ~50 us.
+    std::thread driver([&] {
+        std::vector<Core::Req> slots[2];
+        std::vector<Core::Req> b;
+        for (;;) {
+            bool any = false;
+            for (auto &s : slots) {
+                if (!s.empty()) {
+                    std::this_thread::sleep_for(std::chrono::microseconds(50));
+                    uint64_t bytes = 0;
+                    for (auto &r : s) bytes += r.bytes;
+                    inflight -= bytes;
+                    core.complete(s, AES_OK, Core::now_ns());
+                    s.clear();
+                    any = true;
+                }
+                if (core.take_batch(b)) {
+                    uint64_t bytes = 0;
+                    for (auto &r : b) {
+                        bytes += r.bytes;
+                        if (r.ticket <= last_taken.load()) ++order_violations;
+                        last_taken = r.ticket;
+                    }
+                    uint64_t now = inflight += bytes;
+                    uint64_t m = max_inflight.load();
+                    while (now > m && !max_inflight.compare_exchange_weak(m, now)) {}
+                    s.swap(b);
+                    any = true;
+                }
+            }
+            if (!any) {
+                if (core.closing_and_drained()) break;
+                core.wait_for_work(1000000);
+            }
+        }
+    });
+
+    // Oversize request is rejected outright.
+    uint64_t t;
+    Core::Req big;
+    big.bytes = budget + 1;
+    CHECK(core.submit(std::move(big), &t) == AES_EAGAIN);
+
+    // Submitters.
+    const int nthreads = 4, per = 3000;
+    std::vector<std::vector<uint64_t>> tickets(nthreads);
+    std::vector<std::thread> subs;
+    for (int k = 0; k < nthreads; ++k) {
+        subs.emplace_back([&, k] {
+            std::mt19937_64 g(k);
+            const uint64_t sizes[3] = {64 << 10, 1 << 20, 8 << 20};
+            for (int i = 0; i < per; ++i) {
+                Core::Req r;
+                double u = std::uniform_real_distribution<double>(0, 1)(g);
+                r.bytes = sizes[u < 0.70 ? 0 : u < 0.95 ? 1 : 2];
+                uint64_t tk;
+                CHECK(core.submit(std::move(r), &tk) == AES_OK);
+                tickets[k].push_back(tk);
+            }
+        });
+    }
+    for (auto &s : subs) s.join();
+
+    // Wait for all; each ticket retires exactly once.
+    for (auto &v : tickets)
+        for (uint64_t tk : v) {
+            CHECK(core.wait(tk, 20 * 1000 * 1000) == AES_OK);
+            CHECK(core.poll(tk) == AES_ENOTFOUND);
+        }
+    CHECK(max_inflight.load() <= budget);
+    CHECK(order_violations.load() == 0);
+
+    aes_stats_t st;
+    core.stats(&st);
+    CHECK(st.submitted == uint64_t(nthreads * per));
+    CHECK(st.completed == st.submitted);
+    CHECK(st.rejected == 1);
+    CHECK(st.budget_high_water <= budget && st.budget_high_water > 0);
+    CHECK(st.p50_us > 0 && st.p99_us >= st.p50_us && st.p999_us >= st.p99_us);
+    CHECK(st.queued_now == 0 && st.inflight_now == 0);
+
+    // Unknown ticket, and a wait that times out on a request still queued.
+    CHECK(core.poll(999999999) == AES_ENOTFOUND);
+    core.close();
+    Core::Req late;
+    late.bytes = 16;
+    CHECK(core.submit(std::move(late), &t) == AES_ECLOSED);
+    driver.join();
+
+    // A fresh core with no driver: the request stays pending; cancel fails it.
+    Core idle(budget, 8, budget);
+    Core::Req r;
+    r.bytes = 100;
+    uint64_t tk;
+    CHECK(idle.submit(std::move(r), &tk) == AES_OK);
+    CHECK(idle.poll(tk) == 0);
+    CHECK(idle.wait(tk, 1000) == AES_ETIMEDOUT);
+    idle.cancel_queued(AES_ECANCELED);
+    CHECK(idle.poll(tk) == AES_ECANCELED);
+    std::printf("engine core ok: max in flight %llu of %llu bytes, %llu batches, mean %.1f req/batch\n",
+                (unsigned long long)max_inflight.load(), (unsigned long long)budget,
+                (unsigned long long)st.batches, st.mean_batch_reqs);
+    return 0;
+}

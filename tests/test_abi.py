@@ -97,3 +97,39 @@ def test_launch_cfg_validation():
         rc = A.lib.aes_ctr_crypt_cfg(ctypes.byref(s), bytes(12), 1, 0x1000, 0x2000, 16,
                                      ctypes.byref(cfg), None)
         assert rc == N.AES_EINVAL, kw
+
+
+def test_loadgen_library_exports_its_header():
+    text = open(os.path.join(ROOT, "include", "aesloadgen.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(aes_load_\w+)\s*\(", text)))
+    assert names == ["aes_load_engine", "aes_load_sync"]
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2607_02630_amd", "libaesloadgen.so"))
+    for name in names:
+        assert hasattr(L, name)
+
+
+def test_loadgen_validation_without_device():
+    from paper_2607_02630_amd import loadgen
+    res = loadgen.aes_load_result_t()
+    assert loadgen.lib.aes_load_engine(None, None, 0, None, 0, ctypes.byref(res)) == N.AES_EINVAL
+    assert loadgen.lib.aes_load_sync(None, 0, None, 0, None, ctypes.byref(res)) == N.AES_EINVAL
+
+
+def test_engine_entry_points_reject_null_handles():
+    L = A.lib
+    t = ctypes.c_uint64()
+    assert L.aes_engine_create(None, None) == N.AES_EINVAL
+    assert L.aes_engine_destroy(None) == N.AES_EINVAL
+    assert L.aes_submit(None, None, ctypes.byref(t)) == N.AES_EINVAL
+    assert L.aes_submit_at(None, None, 0, ctypes.byref(t)) == N.AES_EINVAL
+    assert L.aes_poll(None, 1) == N.AES_EINVAL
+    assert L.aes_wait(None, 1, 0) == N.AES_EINVAL
+    assert L.aes_engine_stats(None, None) == N.AES_EINVAL
+    assert L.aes_engine_reset_stats(None) == N.AES_EINVAL
+    assert L.aes_engine_completion_fd(None) == N.AES_EINVAL
+    # Without a GPU the engine cannot start.
+    h = ctypes.c_void_p()
+    assert L.aes_engine_create(None, ctypes.byref(h)) in (N.AES_EDEVICE, N.AES_OK)
+    if h.value:
+        L.aes_engine_destroy(h)

@@ -1,0 +1,174 @@
+"""GPU tests of the serving engine (submit -> poll/wait, continuous batching).
+
+Each result is the same alone and in the mix (tolerance 0 bits): requests of
+the serving size mix run through the engine concurrently, from several
+submitting threads, and every output equals the single-request call on the
+same input and the CPU oracle on sampled blocks.  Also: the byte budget
+holds, oversize requests are refused, ticket semantics, pinned host buffers,
+shutdown drains submitted work, and the completion file descriptor.
+"""
+from __future__ import annotations
+
+import os
+import select
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import log, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+KiB, MiB = 1024, 1 << 20
+
+
+def lib():
+    import paper_2607_02630_amd as A
+    return A
+
+
+def make_requests(torch, n, seed, sizes=W.SERVING_SIZES, mix=W.SERVING_MIX, host=False):
+    g = np.random.default_rng(seed)
+    which = g.choice(len(sizes), size=n, p=mix)
+    lens = [int(sizes[k]) for k in which]
+    total = sum(lens)
+    src = W.device_payload(total, seed)
+    if host:
+        src = src.cpu().pin_memory()
+        dst = torch.zeros(total, dtype=torch.uint8).pin_memory()
+    else:
+        dst = torch.zeros_like(src)
+    A = lib()
+    reqs, offs, pos = [], [], 0
+    for L in lens:
+        key, nonce, ctr0 = g.bytes(16), g.bytes(12), int(g.integers(0, 1 << 32))
+        s = A.aes_expand_key(key)
+        reqs.append((key, nonce, ctr0, s, A.Request(s, nonce, ctr0, src.data_ptr() + pos, dst.data_ptr() + pos, L)))
+        offs.append(pos)
+        pos += L
+    return src, dst, reqs, offs, lens
+
+
+def check_alone_and_oracle(torch, src, dst, reqs, offs, lens, rng):
+    A = lib()
+    dsrc = src.cuda() if not src.is_cuda else src
+    alone = torch.zeros(dsrc.numel(), dtype=torch.uint8, device="cuda")
+    for (key, nonce, ctr0, s, _), o, L in zip(reqs, offs, lens):
+        A.aes_ctr_crypt(s, nonce, ctr0, dsrc.data_ptr() + o, alone.data_ptr() + o, length=L)
+    torch.cuda.synchronize()
+    got = dst.cuda() if not dst.is_cuda else dst
+    assert torch.equal(alone, got), "engine output differs from the single-request call"
+    for i in rng.choice(len(reqs), min(40, len(reqs)), replace=False):
+        key, nonce, ctr0, _, _ = reqs[i]
+        o, L = offs[i], lens[i]
+        nb = L // 16
+        for j in (0, nb - 1, int(rng.integers(0, nb))):
+            a, b = o + 16 * j, o + 16 * j + 16
+            ref = oracle.ctr(key, nonce, (ctr0 + j) & 0xFFFFFFFF, src[a:b].cpu().numpy())
+            assert np.array_equal(got[a:b].cpu().numpy(), ref)
+
+
+def test_same_alone_and_in_the_mix():
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_requests(torch, 600, 1)
+    log(f"engine: {len(reqs)} requests, {sum(lens) / MiB:.1f} MiB")
+    with A.Engine(budget_bytes=4 << 30, n_streams=2) as eng:
+        tickets = [None] * len(reqs)
+
+        def submit_range(lo, hi):
+            for i in range(lo, hi):
+                tickets[i] = eng.submit(reqs[i][4])
+
+        ths = [threading.Thread(target=submit_range, args=(k * 150, (k + 1) * 150)) for k in range(4)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        for t in tickets:
+            eng.wait(t)
+        st = eng.stats()
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+    assert st["batches"] >= 1 and st["p99_us"] >= st["p50_us"] > 0
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(3))
+
+
+def test_budget_is_respected():
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_requests(torch, 120, 2, sizes=(1 * MiB, 8 * MiB), mix=(0.6, 0.4))
+    budget = 16 * MiB
+    with A.Engine(budget_bytes=budget, n_streams=2) as eng:
+        ts = [eng.submit(r[4]) for r in reqs]
+        for t in ts:
+            eng.wait(t)
+        st = eng.stats()
+    assert 0 < st["budget_high_water"] <= budget
+    assert st["batches"] >= sum(lens) // budget
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(4))
+
+
+def test_oversize_and_ticket_semantics():
+    torch = torch_cuda()
+    A = lib()
+    buf = torch.zeros(4 * MiB, dtype=torch.uint8, device="cuda")
+    s = A.aes_expand_key(bytes(16))
+    with A.Engine(budget_bytes=1 * MiB) as eng:
+        with pytest.raises(A.AesError) as e:
+            eng.submit(A.Request(s, bytes(12), 1, buf.data_ptr(), buf.data_ptr(), 2 * MiB))
+        assert e.value.status == -3
+        with pytest.raises(A.AesError) as e:
+            eng.submit(A.Request(s, bytes(12), 1, buf.data_ptr(), buf.data_ptr() + 8, 64))
+        assert e.value.status == -8
+        t = eng.submit(A.Request(s, bytes(12), 1, buf.data_ptr(), buf.data_ptr(), 512 * KiB))
+        eng.wait(t)
+        with pytest.raises(A.AesError) as e:
+            eng.poll(t)                      # retired by wait
+        assert e.value.status == -6
+        with pytest.raises(A.AesError):
+            eng.wait(123456789, 1000)
+        t2 = eng.submit(A.Request(s, bytes(12), 1, buf.data_ptr(), buf.data_ptr(), 0))
+        eng.wait(t2, 5_000_000)
+        st = eng.stats()
+        assert st["rejected"] == 1
+
+
+def test_pinned_host_buffers():
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_requests(torch, 60, 5, sizes=(64 * KiB, 1 * MiB), mix=(0.7, 0.3),
+                                               host=True)
+    with A.Engine(budget_bytes=256 * MiB, host_buffers=True) as eng:
+        ts = [eng.submit(r[4]) for r in reqs]
+        for t in ts:
+            eng.wait(t)
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(6))
+
+
+def test_destroy_drains_submitted_work():
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_requests(torch, 200, 7)
+    eng = A.Engine()
+    for r in reqs:
+        eng.submit(r[4])
+    eng.close()                 # returns after every submitted request ran
+    torch.cuda.synchronize()
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(8))
+
+
+def test_completion_fd_becomes_readable():
+    torch = torch_cuda()
+    A = lib()
+    buf = torch.zeros(MiB, dtype=torch.uint8, device="cuda")
+    s = A.aes_expand_key(bytes(32))
+    with A.Engine() as eng:
+        fd = eng.completion_fd()
+        t = eng.submit(A.Request(s, bytes(12), 7, buf.data_ptr(), buf.data_ptr(), MiB))
+        r, _, _ = select.select([fd], [], [], 10.0)
+        assert fd in r
+        os.read(fd, 8)
+        assert eng.poll(t) or (eng.wait(t) is None)

@@ -112,3 +112,18 @@ def serving_trace(n: int, rate_per_s: float, seed: int | None = None):
     nonces = [g.bytes(12) for _ in range(n)]
     ctr0s = g.integers(0, 1 << 32, size=n, dtype=np.uint64)
     return arrivals, sizes, keys, nonces, ctr0s
+
+
+def device_payload(nbytes: int, seed: int):
+    """Uniform random bytes generated on the GPU (torch's seeded generator),
+    for batches too large to stage from the host; the same bytes can be
+    copied back for the oracle."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    out = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    chunk = 1 << 28
+    for a in range(0, nbytes, chunk):
+        b = min(nbytes, a + chunk)
+        out[a:b] = torch.randint(0, 256, (b - a,), dtype=torch.uint8, device="cuda", generator=g)
+    return out
