@@ -138,6 +138,31 @@ def end_to_end_gbs(torch, A, sched, nonce, payload, reps=5):
     return vals[len(vals) // 2]
 
 
+TT_SOURCES = ("ttable_device.h", "ctr_ttable.hip", "aes_tables.h")
+
+
+def measured_traffic(bits, size, variant):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on this workload and on the kernel sources as they are now."""
+    if (bits, size, variant) != (128, 8 * MiB, 0):
+        return None
+    path = os.path.join(HERE, "profiles", "ctr_ttable_aes128_8MiB_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for name in TT_SOURCES:
+        with open(os.path.join(HERE, "paper_2607_02630_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(W, size, bits, seconds):
     import numpy as np
     import oracle
@@ -206,10 +231,10 @@ def main():
     # (payload in + out); average launch duration from the events above.
     hbm_achieved = 2 * args.size / (ms_per_step * 1e-3) / 1e9
     nr = 10 if args.bits == 128 else 14
-    # LDS-issue roofline of the T-table method (16*Nr lookups of 4 B per
-    # 16-byte block) at the chip's LDS read rate; derivation in the design doc.
-    lds_bytes_per_clk_cu = float(os.environ.get("AESCTR_LDS_BYTES_PER_CLK", 128))
-    lookups_per_s = cus * 2.4e9 * lds_bytes_per_clk_cu / 4
+    # LDS-issue roofline of the T-table method: gfx950 reads 128 B/clk per CU
+    # from LDS (32 banks x 4 B), i.e. 32 random 4-byte lookups per clock; the
+    # method needs 16*Nr lookups per 16-byte block.  Derivation in the design doc.
+    lookups_per_s = cus * 2.4e9 * 32
     alu_peak_gbs = lookups_per_s / (16 * nr) * 16 / 1e9
     result = {
         "metric": "AES-CTR GB/s at 1/8 MiB; batched GB/s + p99 latency vs per-request launch",
@@ -231,7 +256,8 @@ def main():
                    "timed_launch": "captured HIP graph of `steps` launches",
                    "parity_vs_oracle_digest": parity},
         "roofline": {"bound": "alu", "achieved": round(gbs, 3), "peak": round(alu_peak_gbs, 1),
-                     "unit": "GB/s", "frac": round(gbs / alu_peak_gbs, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(gbs / alu_peak_gbs, 4),
+                     "traffic": measured_traffic(args.bits, args.size, args.variant),
                      "note": "payload GB/s vs the LDS-issue ceiling of 16*Nr table lookups per block"},
         "hbm_roofline": {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4)},
@@ -240,6 +266,11 @@ def main():
         "end_to_end_pinned_gbs": round(e2e, 3),
         "device": {"name": props.name, "cus": cus},
     }
+    # Calibration for HBM-traffic counters: a plain copy of the same size
+    # (torch's copy kernel) moves exactly size bytes in and size bytes out.
+    for _ in range(5):
+        outs[1].copy_(ins[1])
+    torch.cuda.synchronize()
     del ins, outs
     torch.cuda.empty_cache()
 
