@@ -163,7 +163,20 @@ def measured_traffic(bits, size, variant):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(W, size, bits, seconds):
+    """The oracle, untuned, on the host cores: repeated passes over one
+    benchmark buffer with all threads (median pass rate over about
+    `seconds`), plus a single-thread figure on a 1 MiB slice."""
     import numpy as np
     import oracle
     key, nonce = W.sweep_key(bits)
@@ -171,17 +184,25 @@ def cpu_baseline(W, size, bits, seconds):
     out = np.empty_like(payload)
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     oracle.ctr_mt_timed(key, nonce, 1, payload[:4096], out[:4096], threads)   # load + warm
-    done, t0 = 0, time.perf_counter()
+    rates, done, t0 = [], 0, time.perf_counter()
     used = threads
     while True:
+        t1 = time.perf_counter()
         used = oracle.ctr_mt_timed(key, nonce, 1, payload, out, threads)
+        rates.append(size / (time.perf_counter() - t1))
         done += size
         if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
-    return {"value": round(done / el / 1e9, 6), "unit": "GB/s", "cores": used, "kind": "oracle",
+    one = payload[:MiB]
+    t1 = time.perf_counter()
+    oracle.ctr_mt_timed(key, nonce, 1, one, out[:MiB], 1)
+    single = one.size / (time.perf_counter() - t1)
+    return {"value": round(_median(rates) / 1e9, 6), "unit": "GB/s", "cores": used, "kind": "oracle",
             "sample": f"{done // size} x {size // MiB} MiB AES-{bits}-CTR buffers of the benchmark "
-                      f"workload through the multithreaded oracle ({el:.1f} s)"}
+                      f"workload through the multithreaded oracle ({el:.1f} s); median pass rate",
+            "single_thread_gbps": round(single / 1e9, 6), "cpu_model": _cpu_model(),
+            "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -412,6 +433,60 @@ def ctypes_byref(x):
     return ctypes.byref(x)
 
 
+def serve_pinned(torch, A, W, g, n_req, npool=2000, budget=4 << 30):
+    """The serving mix with payloads in pinned host memory: the engine's
+    kernels read and write them over PCIe (host_buffers), against the
+    synchronous path that copies each request in, encrypts it, copies it out
+    and synchronises.  Points at 10/50/90% of the engine's saturation rate."""
+    import numpy as np
+    from paper_2607_02630_amd import loadgen
+    which = g.choice(3, size=npool, p=W.SERVING_MIX)
+    lens = np.array(W.SERVING_SIZES, dtype=np.int64)[which]
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    total = int(lens.sum())
+    src = torch.empty(total, dtype=torch.uint8, pin_memory=True)
+    src.numpy()[:] = np.frombuffer(g.bytes(total), dtype=np.uint8)
+    dst = torch.zeros(total, dtype=torch.uint8, pin_memory=True)
+    dev = torch.empty(max(W.SERVING_SIZES), dtype=torch.uint8, device="cuda")
+    scheds = [A.aes_expand_key(g.bytes(16)) for _ in range(npool)]
+    objs = [A.Request(s, g.bytes(12), int(g.integers(0, 1 << 32)), src.data_ptr() + int(o),
+                      dst.data_ptr() + int(o), int(L)) for s, o, L in zip(scheds, offs, lens)]
+    pool = A.make_desc_array(objs)
+    st = torch.cuda.current_stream().cuda_stream
+    out = {"requests_per_point": n_req, "pool_bytes": total}
+    with A.Engine(budget_bytes=budget, n_streams=2, host_buffers=True) as eng:
+        loadgen.run_engine(eng, pool, np.zeros(min(4000, n_req)))         # warm-up
+        sat = loadgen.run_engine(eng, pool, np.zeros(n_req))
+        rate = sat["achieved_rps"]
+        out["saturation"] = {k: round(v, 3) for k, v in sat.items()}
+        log(f"serving (pinned host): saturation {rate:.0f} req/s, {sat['gbps']:.1f} GB/s")
+        points = []
+        for frac in (0.1, 0.5, 0.9):
+            arr = W.serving_trace(n_req, frac * rate)[0]
+            e = loadgen.run_engine(eng, pool, arr)
+            s = loadgen.run_sync_host(pool, arr[:min(n_req, 5000)], dev.data_ptr(), dev.numel(), st)
+            points.append({"offered_frac": frac, "offered_rps": round(frac * rate, 1),
+                           "engine": {k: round(v, 3) for k, v in e.items()},
+                           "sync_per_request": {k: round(v, 3) for k, v in s.items()}})
+            log(f"serving pinned {frac:.0%}: engine p50 {e['p50_us']:.0f} p99 {e['p99_us']:.0f} us "
+                f"{e['gbps']:.1f} GB/s; sync p99 {s['p99_us']:.0f} us {s['gbps']:.1f} GB/s")
+        out["points"] = points
+    # The host buffers hold every pool entry's ciphertext: decrypting them on
+    # the device (same key, nonce, counter) must give the plaintext back.
+    torch.cuda.synchronize()
+    dct = dst.cuda()
+    back = torch.empty_like(dct)
+    for o in objs:
+        off = o.out - dst.data_ptr()
+        A.aes_ctr_crypt(o.sched, o.nonce, o.ctr0, dct.data_ptr() + off, back.data_ptr() + off, length=o.length)
+    torch.cuda.synchronize()
+    out["roundtrip_ok"] = bool(torch.equal(back.cpu(), src))
+    if not out["roundtrip_ok"]:
+        raise SystemExit("pinned-host serving outputs do not decrypt to their inputs")
+    del src, dst, dct, back, dev
+    return out
+
+
 def serve_leg(torch, A, W, n_req=100_000, budget=4 << 30):
     """Open-loop Poisson arrivals at 10/50/90% of the engine's measured
     saturation rate on the serving mix (70% 64 KiB / 25% 1 MiB / 5% 8 MiB,
@@ -454,6 +529,7 @@ def serve_leg(torch, A, W, n_req=100_000, budget=4 << 30):
                 f" sync p99 {s['p99_us']:.0f} us {s['gbps']:.1f} GB/s")
         out["points"] = points
         out["engine_stats"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in eng.stats().items()}
+    out["pinned_host"] = serve_pinned(torch, A, W, g, min(n_req, 20000))
     # Results are the same in the mix as alone: every pool entry's output.
     torch.cuda.synchronize()
     alone = torch.zeros_like(dst)

@@ -36,8 +36,10 @@ typedef struct {
 
 /* Replay arrivals against an engine.  pool: request descriptors reused in
  * round-robin order (i mod npool); arrival_s: n non-decreasing offsets in
- * seconds from the start.  Blocks until every request completed.  The
- * engine's statistics are reset at the start.
+ * seconds from the start.  Up to four submitting threads share the schedule
+ * (arrival i goes to thread i mod T), each spinning until its request's
+ * arrival time; a collector thread retires tickets.  Blocks until every
+ * request completed.  The engine's statistics are reset at the start.
  * Errors: AES_EINVAL (null pointers, npool == 0), or the first error a
  * submission returned (the run stops submitting at that point). */
 int aes_load_engine(aes_engine_t *e, const aes_ctr_desc_t *pool, size_t npool, const double *arrival_s,
@@ -47,6 +49,16 @@ int aes_load_engine(aes_engine_t *e, const aes_ctr_desc_t *pool, size_t npool, c
  * (device buffers).  Errors: AES_EINVAL, or an aes_ctr_crypt error. */
 int aes_load_sync(const aes_ctr_desc_t *pool, size_t npool, const double *arrival_s, size_t n,
                   void *stream, aes_load_result_t *out);
+
+/* The synchronous per-request path for host-resident payloads: the pool's
+ * in/out are pinned host memory (hipHostMalloc); each request is copied to
+ * the device buffer dev_buf (dev_bytes long, at least the largest request),
+ * encrypted there in place, copied back to its out buffer and synchronised,
+ * one at a time, on `stream`.  Errors: AES_EINVAL (null pointers, a request
+ * longer than dev_bytes), AES_EDEVICE (a failed copy), or an aes_ctr_crypt
+ * error. */
+int aes_load_sync_host(const aes_ctr_desc_t *pool, size_t npool, const double *arrival_s, size_t n,
+                       void *dev_buf, size_t dev_bytes, void *stream, aes_load_result_t *out);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,10 @@ def _load():
     L.aes_load_sync.argtypes = [ctypes.POINTER(N.aes_ctr_desc_t), ctypes.c_size_t, dp, ctypes.c_size_t,
                                 ctypes.c_void_p, ctypes.POINTER(aes_load_result_t)]
     L.aes_load_sync.restype = ctypes.c_int
+    L.aes_load_sync_host.argtypes = [ctypes.POINTER(N.aes_ctr_desc_t), ctypes.c_size_t, dp, ctypes.c_size_t,
+                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                     ctypes.POINTER(aes_load_result_t)]
+    L.aes_load_sync_host.restype = ctypes.c_int
     return L
 
 
@@ -56,6 +60,18 @@ def run_sync(pool, arrivals_s: np.ndarray, stream: int) -> dict:
     res = aes_load_result_t()
     rc = lib.aes_load_sync(pool, len(pool), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size,
                            stream, ctypes.byref(res))
+    if rc < 0:
+        raise RuntimeError(N.lib.aes_strerror(rc).decode())
+    return _as_dict(res)
+
+
+def run_sync_host(pool, arrivals_s: np.ndarray, dev_buf: int, dev_bytes: int, stream: int) -> dict:
+    """Synchronous per-request path for pinned-host payloads: copy in,
+    encrypt on the device, copy out, synchronise, one request at a time."""
+    a = np.ascontiguousarray(arrivals_s, dtype=np.float64)
+    res = aes_load_result_t()
+    rc = lib.aes_load_sync_host(pool, len(pool), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size,
+                                dev_buf, dev_bytes, stream, ctypes.byref(res))
     if rc < 0:
         raise RuntimeError(N.lib.aes_strerror(rc).decode())
     return _as_dict(res)

@@ -103,7 +103,7 @@ def test_loadgen_library_exports_its_header():
     text = open(os.path.join(ROOT, "include", "aesloadgen.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = sorted(set(re.findall(r"\b(aes_load_\w+)\s*\(", text)))
-    assert names == ["aes_load_engine", "aes_load_sync"]
+    assert names == ["aes_load_engine", "aes_load_sync", "aes_load_sync_host"]
     L = ctypes.CDLL(os.path.join(ROOT, "paper_2607_02630_amd", "libaesloadgen.so"))
     for name in names:
         assert hasattr(L, name)
@@ -114,6 +114,7 @@ def test_loadgen_validation_without_device():
     res = loadgen.aes_load_result_t()
     assert loadgen.lib.aes_load_engine(None, None, 0, None, 0, ctypes.byref(res)) == N.AES_EINVAL
     assert loadgen.lib.aes_load_sync(None, 0, None, 0, None, ctypes.byref(res)) == N.AES_EINVAL
+    assert loadgen.lib.aes_load_sync_host(None, 0, None, 0, None, 0, None, ctypes.byref(res)) == N.AES_EINVAL
 
 
 def test_engine_entry_points_reject_null_handles():
