@@ -187,9 +187,11 @@ typedef struct {
     int32_t n_streams;          /* concurrent batch launches (0 = 2)           */
     int32_t max_batch_reqs;     /* requests per launch (0 = 4096)              */
     uint64_t max_batch_bytes;   /* payload bytes per launch (0 = budget)       */
-    int32_t key_slots;          /* resident device key schedules (0 = 8192)    */
-    int32_t host_buffers;       /* 1: in/out are host memory; the engine copies
-                                   through resident device buffers             */
+    int32_t key_slots;          /* unused (>= 0): every descriptor carries its
+                                   own expanded key schedule                   */
+    int32_t host_buffers;       /* 1: in/out are pinned host memory
+                                   (hipHostMalloc) that the kernel reads and
+                                   writes directly over PCIe (zero-copy)       */
     int32_t device;             /* HIP device ordinal (-1 = current)           */
     int32_t reserved[5];
 } aes_engine_cfg_t;
@@ -214,6 +216,9 @@ int aes_engine_destroy(aes_engine_t *e);
 
 /* Submit one request (*d copied, its schedule copied).  Never blocks on the
  * device: a request that does not fit the budget now waits in FIFO order.
+ * Takes no lock; when 32768 requests are already queued (admitted requests
+ * do not count) the call yields until the engine takes some.  Thread-safe;
+ * calls racing with aes_engine_destroy are not allowed.
  * Errors: AES_EINVAL, AES_ERANGE, AES_EOVERLAP, AES_EAGAIN (larger than the
  * whole budget), AES_ECLOSED. */
 int aes_submit(aes_engine_t *e, const aes_ctr_desc_t *d, uint64_t *ticket);
@@ -227,10 +232,13 @@ int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t_arrival_ns
 
 /* 1 = done (the ticket is retired by this call), 0 = pending, < 0 = error
  * (AES_ENOTFOUND, AES_EDEVICE if the request's launch failed, AES_ECANCELED).
- * Never blocks. */
+ * Never blocks and takes no lock.  A finished ticket keeps its result until
+ * it is retired or until 2^20 later tickets have been issued (then
+ * AES_ENOTFOUND). */
 int aes_poll(aes_engine_t *e, uint64_t ticket);
 
-/* Block until the ticket completes or timeout_us passes (< 0 = forever).
+/* Block until the ticket completes or timeout_us passes (< 0 = forever):
+ * spins for up to 20 us, then sleeps until a completion signals it.
  * Returns AES_OK and retires the ticket, AES_ETIMEDOUT (ticket stays
  * pending), or an error as aes_poll. */
 int aes_wait(aes_engine_t *e, uint64_t ticket, int64_t timeout_us);

@@ -135,6 +135,111 @@ int main()
     CHECK(idle.wait(tk, 1000) == AES_ETIMEDOUT);
     idle.cancel_queued(AES_ECANCELED);
     CHECK(idle.poll(tk) == AES_ECANCELED);
+    // Back-pressure: with no driver the ring fills; the next submitter waits
+    // until the driver takes requests, then goes on.
+    {
+        Core q(uint64_t(1) << 40, 4096, uint64_t(1) << 40);
+        const uint64_t cap = Core::kQueueCap;
+        std::atomic<uint64_t> done_subs{0};
+        std::thread sub([&] {
+            for (uint64_t i = 0; i < cap + 100; ++i) {
+                Core::Req rq;
+                rq.bytes = 16;
+                uint64_t tk2;
+                CHECK(q.submit(std::move(rq), &tk2) == AES_OK);
+                done_subs.fetch_add(1);
+            }
+        });
+        while (done_subs.load() < cap)
+            std::this_thread::yield();
+        std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        CHECK(done_subs.load() == cap);                   // blocked on the full ring
+        aes_stats_t qs;
+        q.stats(&qs);
+        CHECK(qs.queued_now == cap);
+        std::vector<Core::Req> b2;
+        uint64_t taken = 0, expect = 1;
+        while (taken < cap + 100) {
+            if (q.take_batch(b2)) {
+                for (auto &r2 : b2) CHECK(r2.ticket == expect++);
+                taken += b2.size();
+                q.complete(b2, AES_OK, Core::now_ns());
+            } else {
+                std::this_thread::yield();
+            }
+        }
+        sub.join();
+        // Two threads polling one finished ticket: exactly one retires it.
+        std::atomic<int> ones{0}, notfound{0};
+        std::thread p1([&] { int r1 = q.poll(7); (r1 == 1 ? ones : notfound).fetch_add(1); });
+        std::thread p2([&] { int r2 = q.poll(7); (r2 == 1 ? ones : notfound).fetch_add(1); });
+        p1.join();
+        p2.join();
+        CHECK(ones.load() == 1 && notfound.load() == 1);
+        CHECK(q.wait(8, 0) == AES_OK && q.poll(8) == AES_ENOTFOUND);
+    }
+
+    // A submitter blocked on a full ring gives up with AES_ECLOSED at close;
+    // cancel_queued then fails everything that was queued.
+    {
+        Core q(uint64_t(1) << 40, 4096, uint64_t(1) << 40);
+        std::atomic<int> closed_rc{0};
+        std::atomic<uint64_t> n_ok{0};
+        std::thread sub([&] {
+            for (;;) {
+                Core::Req rq;
+                rq.bytes = 16;
+                uint64_t tk2;
+                int rc2 = q.submit(std::move(rq), &tk2);
+                if (rc2 != AES_OK) {
+                    closed_rc = rc2;
+                    return;
+                }
+                n_ok.fetch_add(1);
+            }
+        });
+        while (n_ok.load() < Core::kQueueCap)
+            std::this_thread::yield();
+        q.close();
+        sub.join();
+        CHECK(closed_rc.load() == AES_ECLOSED);
+        q.cancel_queued(AES_ECANCELED);
+        CHECK(q.poll(1) == AES_ECANCELED && q.poll(Core::kQueueCap) == AES_ECANCELED);
+        CHECK(q.closing_and_drained());
+    }
+
+    // Submission rate with four threads and a draining driver (printed only).
+    {
+        Core q(uint64_t(1) << 40, 4096, uint64_t(1) << 40);
+        std::atomic<bool> fin{false};
+        std::thread drv([&] {
+            std::vector<Core::Req> b3;
+            while (!fin.load() || q.take_batch(b3)) {
+                if (q.take_batch(b3))
+                    q.complete(b3, AES_OK, Core::now_ns());
+                else
+                    std::this_thread::yield();
+            }
+        });
+        const int per2 = 200000;
+        const int64_t t0 = Core::now_ns();
+        std::vector<std::thread> ss;
+        for (int k = 0; k < 4; ++k)
+            ss.emplace_back([&] {
+                for (int i = 0; i < per2; ++i) {
+                    Core::Req rq;
+                    rq.bytes = 65536;
+                    uint64_t tk2;
+                    CHECK(q.submit(std::move(rq), &tk2) == AES_OK);
+                }
+            });
+        for (auto &th : ss) th.join();
+        const double el = (Core::now_ns() - t0) * 1e-9;
+        fin = true;
+        drv.join();
+        std::printf("submit rate, 4 threads: %.2f M/s\n", 4.0 * per2 / el / 1e6);
+    }
+
     std::printf("engine core ok: max in flight %llu of %llu bytes, %llu batches, mean %.1f req/batch\n",
                 (unsigned long long)max_inflight.load(), (unsigned long long)budget,
                 (unsigned long long)st.batches, st.mean_batch_reqs);
