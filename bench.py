@@ -252,11 +252,25 @@ def main():
     # (payload in + out); average launch duration from the events above.
     hbm_achieved = 2 * args.size / (ms_per_step * 1e-3) / 1e9
     nr = 10 if args.bits == 128 else 14
-    # LDS-issue roofline of the T-table method: gfx950 reads 128 B/clk per CU
-    # from LDS (32 banks x 4 B), i.e. 32 random 4-byte lookups per clock; the
-    # method needs 16*Nr lookups per 16-byte block.  Derivation in the design doc.
-    lookups_per_s = cus * 2.4e9 * 32
-    alu_peak_gbs = lookups_per_s / (16 * nr) * 16 / 1e9
+    # Roofline of the cipher kernel.  T-table kernel: bound by LDS issue;
+    # gfx950 reads 128 B/clk per CU from LDS (32 banks x 4 B), i.e. 32 random
+    # 4-byte lookups per clock.  The method needs 16*Nr lookups per 16-byte
+    # block; with counter-mode caching of rounds 1-2 this kernel does 27
+    # fewer (133 for AES-128, 197 for AES-256), and the peak is taken at the
+    # kernel's own count.  Bitsliced kernel: bound by VALU issue (64 lane-ops
+    # per clock per CU, about 814 per AES-128 block).  Derivation in the design doc.
+    clk = 2.4e9
+    if args.variant == 2:
+        valu_per_block = 814 if nr == 10 else 814 * 14 // 10
+        alu_peak_gbs = cus * 64 * clk / valu_per_block * 16 / 1e9
+        alu_note = f"payload GB/s vs the VALU-issue ceiling of {valu_per_block} ops per block"
+        method_peak = None
+    else:
+        lookups = 16 * nr - 27
+        alu_peak_gbs = cus * clk * 32 / lookups * 16 / 1e9
+        method_peak = cus * clk * 32 / (16 * nr) * 16 / 1e9
+        alu_note = (f"payload GB/s vs the LDS-issue ceiling at the kernel's {lookups} table lookups "
+                    f"per block (16*Nr = {16 * nr} without counter-mode caching: {method_peak:.1f} GB/s)")
     result = {
         "metric": "AES-CTR GB/s at 1/8 MiB; batched GB/s + p99 latency vs per-request launch",
         "value": round(gbs, 3),
@@ -279,7 +293,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(gbs, 3), "peak": round(alu_peak_gbs, 1),
                      "unit": "GB/s", "frac": round(gbs / alu_peak_gbs, 4),
                      "traffic": measured_traffic(args.bits, args.size, args.variant),
-                     "note": "payload GB/s vs the LDS-issue ceiling of 16*Nr table lookups per block"},
+                     "note": alu_note},
         "hbm_roofline": {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4)},
         "eager_gbs": round(eager_gbs, 3),

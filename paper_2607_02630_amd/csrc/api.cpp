@@ -79,16 +79,18 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         sh.copies = te.copies;
         sh.grid = te.grid_per_cu * di.num_cus;
     } else if (sh.variant == AES_VARIANT_TTABLE) {
-        // Measured on MI355X: small messages prefer smaller workgroups with
-        // one block per lane; mid sizes two blocks per lane and the 64-copy
-        // table; large ones the 32-copy table.
+        // Measured on MI355X (one workgroup per CU, 32-copy table): small
+        // messages prefer 512-thread workgroups with one block per lane; from
+        // 4 MiB two blocks per lane keep every workgroup busy; from 64 MiB on
+        // four blocks per lane (a 64 KiB chunk per workgroup) are fastest.
         sh.grid = di.num_cus;
+        sh.copies = 32;
         if (len <= (2u << 20)) {
-            sh.bpl = 1; sh.wg = 512; sh.copies = 32;
-        } else if (len <= (64u << 20)) {
-            sh.bpl = 2; sh.wg = 1024; sh.copies = 64;
+            sh.bpl = 1; sh.wg = 512;
+        } else if (len < (64u << 20)) {
+            sh.bpl = 2; sh.wg = 1024;
         } else {
-            sh.bpl = key_bits == 128 ? 2 : 1; sh.wg = 1024; sh.copies = 32;
+            sh.bpl = 4; sh.wg = 1024;
         }
     } else {
         sh.bpl = 1;

@@ -27,20 +27,23 @@ typedef __attribute__((address_space(1))) u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint8_t g_cu8;
 typedef __attribute__((address_space(1))) uint8_t g_u8;
 
+// Blocks [b0, b1) of one request.  The loop trip count is the same for every
+// lane (the round-1/2 sharing needs the whole wave), and lane i of each step
+// holds block s0 + 64*b + i.
 template <int NR, int BPL, bool ALIGNED>
 __device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const CtrArgs &a, uint64_t b0,
                                          uint64_t b1, uint32_t lane)
 {
     const uint64_t nfull = a.len >> 4;
     uint32_t krot[1];   // unused by the 32-copy table
-    for (uint64_t base = b0 + lane; base < b1; base += 64 * BPL) {
+    for (uint64_t s0 = b0; s0 < b1; s0 += 64 * BPL) {
         uint32_t ctr[BPL], ks[BPL][4];
         u32x4 d[BPL];
 #pragma unroll
         for (int b = 0; b < BPL; ++b) {
-            const uint64_t idx = base + 64 * b;
+            const uint64_t idx = s0 + 64 * b + lane;
             ctr[b] = a.ctr0 + static_cast<uint32_t>(idx);
-            if (idx < nfull) {
+            if (idx < b1 && idx < nfull) {
                 if constexpr (ALIGNED) {
                     d[b] = __builtin_nontemporal_load((g_cu32x4 *)(uintptr_t)a.in + idx);
                 } else {
@@ -52,10 +55,13 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const C
                 }
             }
         }
-        keystream<NR, kBatchCopies, BPL>(tt, a, krot, ctr, ks);
+        const WaveGroups w = wave_groups<BPL>(a, a.ctr0 + static_cast<uint32_t>(s0));
+        keystream_wave<NR, kBatchCopies, BPL>(tt, a, krot, ctr, w, ks);
 #pragma unroll
         for (int b = 0; b < BPL; ++b) {
-            const uint64_t idx = base + 64 * b;
+            const uint64_t idx = s0 + 64 * b + lane;
+            if (idx >= b1)
+                continue;
             const u32x4 k = u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]};
             if (idx < nfull) {
                 if constexpr (ALIGNED) {
@@ -68,7 +74,7 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const C
 #pragma unroll
                     for (int i = 0; i < 16; ++i) p[i] = tmp[i];
                 }
-            } else if (idx == nfull && idx < b1) {
+            } else if (idx == nfull) {
                 // Final partial block: leading bytes of its keystream block.
                 const uint32_t tail = static_cast<uint32_t>(a.len & 15);
                 g_cu8 *src = (g_cu8 *)(uintptr_t)a.in + 16 * idx;

@@ -32,46 +32,58 @@ __device__ __forceinline__ void store_block(const CtrArgs &a, uint64_t idx, u32x
     }
 }
 
+// Block of lane `lane`, slot b, in the chunk at `start`: wave `wave` owns
+// the 64 x BPL consecutive blocks from start + 64 BPL wave, so each load or
+// store instruction still covers 1 KiB of contiguous payload.
+template <int BPL>
+__device__ __forceinline__ uint64_t block_of(uint64_t start, uint32_t wave, uint32_t lane, int b)
+{
+    return start + 64u * (wave * BPL + b) + lane;
+}
+
 template <bool ALIGNED, int BPL>
-__device__ __forceinline__ void prefetch(const u32x4 *src, uint64_t base, uint64_t wg, uint64_t nfull,
-                                         uint64_t last, u32x4 (&d)[BPL])
+__device__ __forceinline__ void prefetch(const u32x4 *src, uint64_t start, uint32_t wave, uint32_t lane,
+                                         uint64_t nfull, uint64_t last, u32x4 (&d)[BPL])
 {
 #pragma unroll
     for (int b = 0; b < BPL; ++b) {
-        const uint64_t idx = base + b * wg;
+        const uint64_t idx = block_of<BPL>(start, wave, lane, b);
         d[b] = load_block<ALIGNED>(src, idx < nfull ? idx : last);
     }
 }
 
-// Keystream of the chunk at `start` XORed into the data d already loaded.
 template <int NR, int COPIES, int BPL, bool ALIGNED>
 __device__ __forceinline__ void chunk_step(const TTable<COPIES> &tt, const CtrArgs &a, const uint32_t *krot,
-                                           uint64_t start, uint64_t wg, uint64_t nfull, const u32x4 (&d)[BPL])
+                                           uint64_t start, uint64_t chunk, uint32_t wave, uint32_t lane,
+                                           uint64_t nfull, const WaveGroups &w, const u32x4 (&d)[BPL])
 {
-    const uint64_t base = start + threadIdx.x;
     uint32_t ctr[BPL], ks[BPL][4];
 #pragma unroll
     for (int b = 0; b < BPL; ++b)
-        ctr[b] = a.ctr0 + static_cast<uint32_t>(base + b * wg);
-    keystream<NR, COPIES, BPL>(tt, a, krot, ctr, ks);
-    if (start + wg * BPL <= nfull) {
+        ctr[b] = a.ctr0 + static_cast<uint32_t>(block_of<BPL>(start, wave, lane, b));
+    keystream_wave<NR, COPIES, BPL>(tt, a, krot, ctr, w, ks);
+    if (start + chunk <= nfull) {
 #pragma unroll
         for (int b = 0; b < BPL; ++b)
-            store_block<ALIGNED>(a, base + b * wg, d[b] ^ u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]});
+            store_block<ALIGNED>(a, block_of<BPL>(start, wave, lane, b),
+                                 d[b] ^ u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]});
     } else {
 #pragma unroll
         for (int b = 0; b < BPL; ++b) {
-            const uint64_t idx = base + b * wg;
+            const uint64_t idx = block_of<BPL>(start, wave, lane, b);
             if (idx < nfull)
                 store_block<ALIGNED>(a, idx, d[b] ^ u32x4{ks[b][0], ks[b][1], ks[b][2], ks[b][3]});
         }
     }
 }
 
-// Loop step over a workgroup chunk of wg * BPL blocks: thread t handles
-// blocks base + t + b * wg.  The loads of the next chunk are issued before
-// this chunk's keystream is computed (the keystream does not depend on the
-// data), so HBM latency hides behind the table lookups.
+// The wave's first counter in the chunk at `start` (wave-uniform).
+template <int BPL>
+__device__ __forceinline__ uint32_t first_ctr(const CtrArgs &a, uint64_t start, uint32_t wave)
+{
+    return a.ctr0 + static_cast<uint32_t>(start + 64u * wave * BPL);
+}
+
 template <int NR, int COPIES, int BPL, int WG, bool ALIGNED>
 __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
 {
@@ -88,20 +100,21 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     // no branch separates these loads from the table reads (a branch would
     // make the compiler wait for every load before the LDS writes).  With no
     // whole block at all, the loads read a dummy block instead.
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t chunk = wg * BPL;
     uint32_t tv[kFillStores / WG];
     fill_read<WG>(tv);
     const uint64_t last = nfull ? nfull - 1 : 0;
     const u32x4 *src = nfull ? reinterpret_cast<const u32x4 *>(a.in) : &g_dummy_block;
     u32x4 d[BPL];
-#pragma unroll
-    for (int b = 0; b < BPL; ++b) {
-        const uint64_t idx = start + threadIdx.x + b * wg;
-        d[b] = load_block<ALIGNED>(src, idx < nfull ? idx : last);
-    }
+    prefetch<ALIGNED, BPL>(src, start, wave, lane, nfull, last, d);
+    // The first chunk's group constants need only the constant tables: the
+    // scalar unit computes them while the table reads are in flight.
+    WaveGroups w = wave_groups<BPL>(a, first_ctr<BPL>(a, start, wave));
     fill_write<COPIES, WG>(lds, tv);
     __syncthreads();
 
-    const uint32_t lane = threadIdx.x & 63;
     const uint32_t k = COPIES == 32 ? (lane & 31) : lane;
     TTable<COPIES> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
 
@@ -117,17 +130,19 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     // register copy forces an early wait on the loads in flight.
     u32x4 e[BPL];
     if (start < nfull) {
-        prefetch<ALIGNED, BPL>(src, start + step + threadIdx.x, wg, nfull, last, e);
-        chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, wg, nfull, d);
+        prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, e);
+        chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
         start += step;
         while (start < nfull) {
-            prefetch<ALIGNED, BPL>(src, start + step + threadIdx.x, wg, nfull, last, d);
-            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, wg, nfull, e);
+            prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, d);
+            w = wave_groups<BPL>(a, first_ctr<BPL>(a, start, wave));
+            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, e);
             start += step;
             if (!(start < nfull))
                 break;
-            prefetch<ALIGNED, BPL>(src, start + step + threadIdx.x, wg, nfull, last, e);
-            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, wg, nfull, d);
+            prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, e);
+            w = wave_groups<BPL>(a, first_ctr<BPL>(a, start, wave));
+            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
             start += step;
         }
     }

@@ -28,6 +28,25 @@ namespace {
 
 __constant__ Tables c_tables = build_tables();
 
+// All four round tables, T_t[x] = rotl(T0[x], 8t), for the scalar unit (it
+// has no rotate): the wave-uniform group constants of rounds 1-2 read them
+// with scalar loads.
+struct RoundTables {
+    uint32_t t[4][256];
+};
+
+constexpr RoundTables build_round_tables()
+{
+    RoundTables r{};
+    const Tables b = build_tables();
+    for (int t = 0; t < 4; ++t)
+        for (int x = 0; x < 256; ++x)
+            r.t[t][x] = rotl32(b.t0[x], 8 * t);
+    return r;
+}
+
+__constant__ RoundTables c_round = build_round_tables();
+
 constexpr int kLdsWords = 32768;   // 128 KiB
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -179,6 +198,104 @@ __device__ __forceinline__ void keystream(const TTable<COPIES> &tt, const CtrArg
     }
 #pragma unroll
     for (int r = 2; r < NR; ++r) {
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+            tt.round(s[b], o[b], &a.rk[4 * r], &krot[4 * r]);
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[b][c] = o[b][c];
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+        tt.last_round(s[b], ks[b], &a.rk[4 * NR]);
+}
+
+// ---- Rounds 1-2 shared by a wave ------------------------------------------
+//
+// Beyond the per-request constant k1, the counter's top three bytes change
+// only every 256 blocks.  Within a "group" of counters with equal bits 31..8
+// only byte 3 of x = bswap(ctr) ^ x0 varies, so of the round-1 output only
+// column 0, s1_0 = k1[0] ^ T3[x.b3], varies; s1_1 = k1[1] ^ T2[x.b2],
+// s1_2 = k1[2] ^ T1[x.b1], s1_3 = k1[3] ^ T0[x.b0] are group constants.  After
+// ShiftRows every round-2 column takes exactly one byte of s1_0, so
+//   s2_c = G_c ^ T_r(c)[byte r(c) of s1_0],  r(c) = (4 - c) mod 4,
+// with G_c = rk2_c ^ (the three T-table terms from s1_1..s1_3).  Rounds 1-2
+// then cost 5 lookups per block instead of 20.  A wave works on 64 x N
+// consecutive counters (N <= 4), which span at most two groups; it computes
+// their G once per step on the scalar unit.
+
+// T_t[byte R of v] from the constant round tables; with a wave-uniform v
+// this is one s_bfe and one s_load on the scalar unit, off the VALU and LDS
+// pipes that the per-block rounds saturate.
+template <int T, int R>
+__device__ __forceinline__ uint32_t ctab(uint32_t v)
+{
+    return c_round.t[T][(v >> (8 * R)) & 255u];
+}
+
+// Round-2 group constants G_0..G_3 of counter group g (wave-uniform): G_c is
+// rk2_c xor the row-R terms T_R[byte R of s1_(c+R mod 4)] from the three
+// group-constant columns of round 1.  Bytes 0..2 of x = bswap(ctr) ^ x0 are
+// the counter's bits 31..24, 23..16 and 15..8, i.e. bytes 2, 1, 0 of g.
+__device__ __forceinline__ void group_consts(const CtrArgs &a, uint32_t g, uint32_t G[4])
+{
+    const uint32_t s1 = a.k1[1] ^ ctab<2, 0>(g ^ (a.x0 >> 16));   // T2[x.b2]
+    const uint32_t s2 = a.k1[2] ^ ctab<1, 1>(g ^ a.x0);            // T1[x.b1]
+    const uint32_t s3 = a.k1[3] ^ ctab<0, 2>(g ^ (a.x0 << 16));   // T0[x.b0]
+    G[0] = a.rk[8] ^ ctab<1, 1>(s1) ^ ctab<2, 2>(s2) ^ ctab<3, 3>(s3);
+    G[1] = a.rk[9] ^ ctab<0, 0>(s1) ^ ctab<1, 1>(s2) ^ ctab<2, 2>(s3);
+    G[2] = a.rk[10] ^ ctab<0, 0>(s2) ^ ctab<1, 1>(s3) ^ ctab<3, 3>(s1);
+    G[3] = a.rk[11] ^ ctab<0, 0>(s3) ^ ctab<2, 2>(s1) ^ ctab<3, 3>(s2);
+}
+
+// The group constants one wave needs: its N x 64 counters are first + i
+// (lane i mod 64, block i / 64), so they reach at most the next group.
+struct WaveGroups {
+    uint32_t gA;
+    uint32_t GA[4], GB[4];
+};
+
+template <int N>
+__device__ __forceinline__ WaveGroups wave_groups(const CtrArgs &a, uint32_t first)
+{
+    static_assert(64 * N <= 256, "a wave's counters must span at most two groups");
+    WaveGroups w;
+    w.gA = first >> 8;
+    const uint32_t gB = (first + 64u * N - 1u) >> 8;
+    group_consts(a, w.gA, w.GA);
+    if (gB != w.gA) {
+        group_consts(a, gB, w.GB);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w.GB[c] = w.GA[c];
+    }
+    return w;
+}
+
+// Keystream of N blocks per lane, lane i / block b holding counter
+// first + 64 b + i where w = wave_groups<N>(a, first).  Every lane of the
+// wave must be active.
+template <int NR, int COPIES, int N>
+__device__ __forceinline__ void keystream_wave(const TTable<COPIES> &tt, const CtrArgs &a, const uint32_t *krot,
+                                               const uint32_t *ctr, const WaveGroups &w, uint32_t (*ks)[4])
+{
+    uint32_t s[N][4], o[N][4];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        const bool in_b = (ctr[b] >> 8) != w.gA;
+        uint32_t G[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) G[c] = in_b ? w.GB[c] : w.GA[c];
+        const uint32_t x = vperm(ctr[b], ctr[b], 0x00010203u) ^ a.x0;
+        const uint32_t s10 = a.k1[0] ^ tt.template get<3, 3>(x);
+        s[b][0] = G[0] ^ tt.template get<0, 0>(s10);
+        s[b][1] = G[1] ^ tt.template get<3, 3>(s10);
+        s[b][2] = G[2] ^ tt.template get<2, 2>(s10);
+        s[b][3] = G[3] ^ tt.template get<1, 1>(s10);
+    }
+#pragma unroll
+    for (int r = 3; r < NR; ++r) {
 #pragma unroll
         for (int b = 0; b < N; ++b)
             tt.round(s[b], o[b], &a.rk[4 * r], &krot[4 * r]);

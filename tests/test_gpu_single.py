@@ -125,11 +125,14 @@ def test_in_place(variant):
     assert np.array_equal(to_host(buf), oracle.ctr(key, nonce, 1, data))
 
 
+@pytest.mark.parametrize("klen", [16, 32])
 @pytest.mark.parametrize("variant", [1, 2], ids=["tt", "bs"])
-@pytest.mark.parametrize("ctr0", [0xFFFFFFFF, 0xFFFFFF00, 0xFFFFFFF0])
-def test_counter_wrap(variant, ctr0):
+@pytest.mark.parametrize("ctr0", [0xFFFFFFFF, 0xFFFFFF00, 0xFFFFFFF0, 0x7FFFFF00, 0x80000013, 0xC0FFEE00])
+def test_counter_wrap(variant, ctr0, klen):
+    """Counters that wrap mod 2^32, and counters at and above 2^31 (where a
+    signed shift of the counter would corrupt its high bits)."""
     g = np.random.default_rng(ctr0 & 0xFFF)
-    key, nonce = g.bytes(32), g.bytes(12)
+    key, nonce = g.bytes(klen), g.bytes(12)
     data = W.payload(g, 16 * 700 + 9)
     got = gpu_crypt(key, nonce, ctr0, data, cfg=lib().launch_cfg(variant=variant))
     assert np.array_equal(got, oracle.ctr(key, nonce, ctr0, data))
