@@ -138,7 +138,7 @@ def end_to_end_gbs(torch, A, sched, nonce, payload, reps=5):
     return vals[len(vals) // 2]
 
 
-TT_SOURCES = ("ttable_device.h", "ctr_ttable.hip", "aes_tables.h")
+TT_SOURCES = ("ttable_device.h", "ctr_ttable.hip", "aes_tables.h", "api.cpp")
 
 
 def measured_traffic(bits, size, variant):
