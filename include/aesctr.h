@@ -19,6 +19,10 @@
  *   - Return value: AES_OK (0) or a negative aes_status_t.  aes_strerror()
  *     names it.  Argument errors are reported before any device work.
  *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *   - The library links libamdhip64.so.7.  A process must hold one HIP
+ *     runtime: where another component brings its own copy (PyTorch's wheels
+ *     ship one under torch/lib), load that component first so this library
+ *     binds to the same copy; streams of one runtime mean nothing to another.
  *   - "device pointer" means memory of the current HIP device (hipMalloc,
  *     a torch CUDA tensor, ...).  Calls that take device pointers are
  *     asynchronous on the given stream; buffers must stay valid until the
@@ -57,6 +61,12 @@ typedef enum {
 
 /* Human-readable name of a status value (static string, never NULL). */
 const char *aes_strerror(int status);
+
+/* Name of the HIP error (e.g. "hipErrorOutOfMemory") behind the calling
+ * thread's latest AES_EDEVICE, or "hipSuccess" if there was none; a static
+ * string, never NULL.  Errors met by an engine's driver thread are recorded
+ * on that thread and surface as AES_EDEVICE tickets. */
+const char *aes_last_device_error(void);
 
 /* ---------------------------------------------------------------------- */
 /* Key schedule (FIPS-197 Sec. 5.2)                                        */

@@ -23,6 +23,8 @@ class AesError(RuntimeError):
     def __init__(self, status: int, where: str = ""):
         self.status = status
         msg = lib.aes_strerror(status).decode()
+        if status == N.AES_EDEVICE:
+            msg += f" ({lib.aes_last_device_error().decode()})"
         super().__init__(f"{where}: {msg}" if where else msg)
 
 

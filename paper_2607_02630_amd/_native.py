@@ -71,6 +71,7 @@ class aes_stats_t(ctypes.Structure):
 # Every exported name and its (restype, argtypes).
 SIGNATURES = {
     "aes_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "aes_last_device_error": (ctypes.c_char_p, []),
     "aes_expand_key": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(aes_sched_t)]),
     "aes_ctr_crypt": (ctypes.c_int, [ctypes.POINTER(aes_sched_t), ctypes.c_char_p, ctypes.c_uint32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -98,7 +99,21 @@ SIGNATURES = {
 }
 
 
+def _bind_torch_runtime() -> None:
+    """One HIP runtime per process.  PyTorch ships its own libamdhip64 and
+    libhsa-runtime64 (sonames libamdhip64.so.7 / libhsa-runtime64.so.1) but
+    asks for them by another file name, so if this library loaded first, with
+    ROCm's copies, PyTorch would load a second pair: two runtimes whose
+    streams and devices do not mix.  Loading PyTorch first makes this
+    library's dependencies resolve to PyTorch's already-loaded copies."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    _bind_torch_runtime()
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build the HIP library first "

@@ -59,6 +59,16 @@ struct DeviceInfo {
 };
 int device_info(DeviceInfo *out);   // AES_OK or AES_EDEVICE
 
+// Device-error bookkeeping for aes_last_device_error(): the HIP error behind
+// the calling thread's latest AES_EDEVICE.  note_device_error() keeps e if it
+// is an error; device_error() takes (and clears) HIP's pending error, keeps
+// it and returns AES_EDEVICE.  Launchers clear HIP's pending error before a
+// launch (it may have been left by other code in the process) and read it
+// back with launch_status().
+void note_device_error(hipError_t e);
+int device_error();
+int launch_status();
+
 // Argument checks shared by the entry points (AES_OK or an error status).
 int check_sched(const aes_sched_t *s);
 int check_buffers(const void *in, const void *out, uint64_t len);

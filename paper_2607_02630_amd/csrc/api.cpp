@@ -14,14 +14,36 @@ constexpr int kMaxDevices = 64;
 std::mutex g_dev_mu;
 DeviceInfo g_dev[kMaxDevices];
 bool g_dev_ok[kMaxDevices];
+thread_local hipError_t t_last_device_error = hipSuccess;
 
 }  // namespace
+
+void note_device_error(hipError_t e)
+{
+    if (e != hipSuccess)
+        t_last_device_error = e;
+}
+
+int device_error()
+{
+    note_device_error(hipGetLastError());
+    return AES_EDEVICE;
+}
+
+int launch_status()
+{
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        return AES_OK;
+    t_last_device_error = e;
+    return AES_EDEVICE;
+}
 
 int device_info(DeviceInfo *out)
 {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EDEVICE;
     }
     std::lock_guard<std::mutex> lk(g_dev_mu);
@@ -31,7 +53,7 @@ int device_info(DeviceInfo *out)
         if (hipDeviceGetAttribute(&d.num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipDeviceGetAttribute(&d.max_lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
                 hipSuccess) {
-            (void)hipGetLastError();
+            note_device_error(hipGetLastError());
             return AES_EDEVICE;
         }
         g_dev[dev] = d;
@@ -120,6 +142,11 @@ static void clamp_grid(Shape *sh, uint64_t len)
 }  // namespace aesctr
 
 using namespace aesctr;
+
+extern "C" const char *aes_last_device_error(void)
+{
+    return hipGetErrorName(t_last_device_error);
+}
 
 extern "C" const char *aes_strerror(int status)
 {

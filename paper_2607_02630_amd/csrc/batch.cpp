@@ -82,7 +82,7 @@ BatchCtx *get_ctx(int device, void *stream, int *rc)
     BatchCtx *c = new BatchCtx();
     *rc = init_ctx(c, device);
     if (*rc != AES_OK) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return nullptr;   // partially initialised context is leaked deliberately
     }
     g_ctx[key] = c;
@@ -127,7 +127,7 @@ int build_graph(BatchCtx *c, int s, int grid, int bpl)
     }
     (void)hipStreamDestroy(cap);
     if (rc != AES_OK) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         sg.exec = nullptr;
         return rc;
     }
@@ -201,7 +201,7 @@ int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, 
         const int slot = c->next_slot;
         c->next_slot = (c->next_slot + 1) % kSlots;
         if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
-            (void)hipGetLastError();
+            note_device_error(hipGetLastError());
             return AES_EDEVICE;
         }
         const size_t bytes = stage(c->staging[slot], recs + first, m, tile_blocks);
@@ -216,19 +216,19 @@ int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, 
             if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
                                                   hipMemcpyHostToDevice) != hipSuccess ||
                 hipGraphLaunch(sg.exec, st) != hipSuccess) {
-                (void)hipGetLastError();
+                note_device_error(hipGetLastError());
                 return AES_EDEVICE;
             }
         } else {
             if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
-                (void)hipGetLastError();
+                note_device_error(hipGetLastError());
                 return AES_EDEVICE;
             }
             if ((rc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, st)) != AES_OK)
                 return rc;
         }
         if (hipEventRecord(c->done[slot], st) != hipSuccess) {
-            (void)hipGetLastError();
+            note_device_error(hipGetLastError());
             return AES_EDEVICE;
         }
         c->used[slot] = true;
@@ -281,7 +281,7 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EDEVICE;
     }
     if (cs != hipStreamCaptureStatusNone)

@@ -170,12 +170,13 @@ int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream
         return AES_EINVAL;
     const uint8_t *t = static_cast<const uint8_t *>(dev_table);
     uint32_t *ctr = reinterpret_cast<uint32_t *>(const_cast<uint8_t *>(t) + offsetof(BatchHeader, next));
+    (void)hipGetLastError();   // not ours: left by earlier calls
     switch (bpl) {
     case 1: hipLaunchKernelGGL(ctr_batch_kernel<1>, dim3(grid), dim3(kBatchWG), 0, st, t, ctr); break;
     case 2: hipLaunchKernelGGL(ctr_batch_kernel<2>, dim3(grid), dim3(kBatchWG), 0, st, t, ctr); break;
     default: return AES_EINVAL;
     }
-    return hipGetLastError() == hipSuccess ? AES_OK : AES_EDEVICE;
+    return launch_status();
 }
 
 }  // namespace aesctr

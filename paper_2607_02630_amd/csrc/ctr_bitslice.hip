@@ -292,11 +292,12 @@ template <int NR>
 int launch_nr(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 3) == 0;
+    (void)hipGetLastError();   // not ours: left by earlier calls
     if (aligned)
         hipLaunchKernelGGL((ctr_bitslice_kernel<NR, true>), dim3(sh.grid), dim3(sh.wg), 0, st, a);
     else
         hipLaunchKernelGGL((ctr_bitslice_kernel<NR, false>), dim3(sh.grid), dim3(sh.wg), 0, st, a);
-    return hipGetLastError() == hipSuccess ? AES_OK : AES_EDEVICE;
+    return launch_status();
 }
 
 }  // namespace

@@ -163,11 +163,12 @@ template <int NR, int COPIES, int BPL, int WG>
 int launch_w(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
+    (void)hipGetLastError();   // not ours: left by earlier calls
     if (aligned)
         hipLaunchKernelGGL((ctr_ttable_kernel<NR, COPIES, BPL, WG, true>), dim3(sh.grid), dim3(WG), 0, st, a);
     else
         hipLaunchKernelGGL((ctr_ttable_kernel<NR, COPIES, BPL, WG, false>), dim3(sh.grid), dim3(WG), 0, st, a);
-    return hipGetLastError() == hipSuccess ? AES_OK : AES_EDEVICE;
+    return launch_status();
 }
 
 template <int NR, int COPIES, int BPL>

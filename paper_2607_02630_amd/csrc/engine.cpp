@@ -31,6 +31,7 @@
 using aesctr::BatchDesc;
 using Core = aesctr::EngineCore<BatchDesc>;
 using Req = Core::Req;
+using aesctr::note_device_error;
 
 struct aes_engine {
     aes_engine(uint64_t budget, size_t max_reqs, uint64_t max_bytes) : core(budget, max_reqs, max_bytes) {}
@@ -82,7 +83,7 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
     if (rc != AES_OK)
         return rc;
     if (hipEventRecord(e->events[s], e->streams[s]) != hipSuccess) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EDEVICE;
     }
     return AES_OK;
@@ -91,7 +92,7 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
 void drive(aes_engine *e)
 {
     if (hipSetDevice(e->device) != hipSuccess) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         e->core.close();
         e->core.cancel_queued(AES_EDEVICE);
         return;
@@ -111,7 +112,7 @@ void drive(aes_engine *e)
                 continue;
             const int status = q == hipSuccess ? AES_OK : AES_EDEVICE;
             if (q != hipSuccess)
-                (void)hipGetLastError();
+                note_device_error(hipGetLastError());
             const int64_t now = Core::now_ns();
             e->core.complete(e->inflight[s], status, now);
             e->inflight[s].clear();
@@ -166,18 +167,18 @@ extern "C" int aes_engine_create(const aes_engine_cfg_t *cfg, aes_engine_t **out
 
     int dev = c.device;
     if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EDEVICE;
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EDEVICE;
     }
     int prev = -1;
     (void)hipGetDevice(&prev);
     if (hipSetDevice(dev) != hipSuccess) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EDEVICE;
     }
     aesctr::DeviceInfo di;
@@ -210,7 +211,7 @@ extern "C" int aes_engine_create(const aes_engine_cfg_t *cfg, aes_engine_t **out
     if (prev >= 0)
         (void)hipSetDevice(prev);
     if (rc != AES_OK) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         for (hipStream_t st : e->streams)
             (void)hipStreamDestroy(st);
         for (hipEvent_t ev : e->events)
@@ -256,7 +257,7 @@ int host_to_device(const void *p, uint64_t *dev)
 {
     hipPointerAttribute_t at{};
     if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-        (void)hipGetLastError();
+        note_device_error(hipGetLastError());
         return AES_EINVAL;
     }
     if (at.type != hipMemoryTypeHost || !at.devicePointer)
