@@ -109,14 +109,41 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     const u32x4 *src = nfull ? reinterpret_cast<const u32x4 *>(a.in) : &g_dummy_block;
     u32x4 d[BPL];
     prefetch<ALIGNED, BPL>(src, start, wave, lane, nfull, last, d);
-    // The first chunk's group constants need only the constant tables: the
-    // scalar unit computes them while the table reads are in flight.
-    WaveGroups w = wave_groups<BPL>(a, first_ctr<BPL>(a, start, wave));
     fill_write<COPIES, WG>(lds, tv);
     __syncthreads();
 
     const uint32_t k = COPIES == 32 ? (lane & 31) : lane;
     TTable<COPIES> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
+
+    // Group constants of the first chunk: wave 0 computes every group the
+    // workgroup's chunk touches (one lane each, from the LDS tables) and the
+    // waves pick theirs up after a second barrier.  Later chunks compute
+    // their own on the scalar unit while other waves keep the pipes busy.
+    static_assert(WG * BPL <= 4096, "a chunk must span at most kChunkGroups groups");
+    __shared__ u32x4 s_groups[kChunkGroups];
+    const uint32_t chunk_first = a.ctr0 + static_cast<uint32_t>(start);
+    const uint32_t g0 = chunk_first >> 8;
+    if (wave == 0) {
+        const uint32_t ng = ((chunk_first & 255u) + WG * BPL + 255u) >> 8;
+        if (lane < ng) {
+            uint32_t G[4];
+            group_consts_lds(tt, a, (g0 + lane) & 0xffffffu, G);
+            s_groups[lane] = u32x4{G[0], G[1], G[2], G[3]};
+        }
+    }
+    __syncthreads();
+    WaveGroups w;
+    {
+        const uint32_t first = first_ctr<BPL>(a, start, wave);
+        w.gA = first >> 8;
+        const u32x4 ga = s_groups[(w.gA - g0) & 0xffffffu];
+        const u32x4 gb = s_groups[(((first + 64u * BPL - 1u) >> 8) - g0) & 0xffffffu];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            w.GA[c] = ga[c];
+            w.GB[c] = gb[c];
+        }
+    }
 
     // rotr(rk, 8) for the two-table fold; uniform, lives in scalar registers.
     uint32_t krot[60];

@@ -249,6 +249,26 @@ __device__ __forceinline__ void group_consts(const CtrArgs &a, uint32_t g, uint3
     G[3] = a.rk[11] ^ ctab<0, 0>(s3) ^ ctab<2, 2>(s1) ^ ctab<3, 3>(s2);
 }
 
+// The same constants from the LDS tables, for a per-lane group g: the first
+// chunk of a launch has every wave of a workgroup start at once, and one
+// wave computing all of the workgroup's groups (a lane each) costs less than
+// sixteen waves queueing on the CU's one scalar unit.
+template <int COPIES>
+__device__ __forceinline__ void group_consts_lds(const TTable<COPIES> &tt, const CtrArgs &a, uint32_t g,
+                                                 uint32_t G[4])
+{
+    const uint32_t s1 = a.k1[1] ^ tt.template get<2, 0>(g ^ (a.x0 >> 16));
+    const uint32_t s2 = a.k1[2] ^ tt.template get<1, 1>(g ^ a.x0);
+    const uint32_t s3 = a.k1[3] ^ tt.template get<0, 2>(g ^ (a.x0 << 16));
+    G[0] = a.rk[8] ^ tt.template get<1, 1>(s1) ^ tt.template get<2, 2>(s2) ^ tt.template get<3, 3>(s3);
+    G[1] = a.rk[9] ^ tt.template get<0, 0>(s1) ^ tt.template get<1, 1>(s2) ^ tt.template get<2, 2>(s3);
+    G[2] = a.rk[10] ^ tt.template get<0, 0>(s2) ^ tt.template get<1, 1>(s3) ^ tt.template get<3, 3>(s1);
+    G[3] = a.rk[11] ^ tt.template get<0, 0>(s3) ^ tt.template get<2, 2>(s1) ^ tt.template get<3, 3>(s2);
+}
+
+// Most groups one workgroup chunk of up to 4096 consecutive counters spans.
+constexpr int kChunkGroups = 17;
+
 // The group constants one wave needs: its N x 64 counters are first + i
 // (lane i mod 64, block i / 64), so they reach at most the next group.
 struct WaveGroups {
