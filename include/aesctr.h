@@ -160,8 +160,10 @@ typedef struct {
 int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream);
 
 /* Batch launch shape: tile_bytes (bytes of a request one wave-tile covers,
- * multiple of 1024), wg_size, grid, blocks_per_lane; zero = tuned default.
- * use_graph: 1 = captured graph (default), 0 = plain copy + launch. */
+ * multiple of 1024), wg_size, grid, blocks_per_lane; zero = default (64 KiB
+ * tiles, 2 blocks per lane, 1024-thread workgroups, one per CU, unless a
+ * tune cache says otherwise).  use_graph: 1 = captured graph, 0 = plain copy
+ * + launch; a call without cfg uses the graph. */
 typedef struct {
     int32_t tile_bytes;
     int32_t wg_size;

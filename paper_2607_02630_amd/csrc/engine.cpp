@@ -39,7 +39,6 @@ struct aes_engine {
     Core core;
     int device = 0;
     int num_cus = 0;
-    int tile_bytes = 16384;
     int host_buffers = 0;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
@@ -65,12 +64,22 @@ void notify_fd(int fd)
 int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vector<BatchDesc> &recs)
 {
     recs.resize(batch.size());
-    uint64_t tiles = 0;
-    const uint64_t tile_blocks = static_cast<uint64_t>(e->tile_bytes / 16);
+    uint64_t bytes = 0;
     for (size_t i = 0; i < batch.size(); ++i) {
         recs[i] = batch[i].rec;
-        tiles += ((batch[i].rec.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
+        bytes += batch[i].rec.len;
     }
+    // Tile size per batch: large batches take 64 KiB tiles (fewer claims,
+    // measured fastest on the 4096-request batch), small ones shrink the tile
+    // down to 16 KiB so that every wave of the chip still finds work.
+    const uint64_t waves = static_cast<uint64_t>(e->num_cus) * 16;
+    uint64_t tile = 65536;
+    while (tile > 16384 && bytes / tile < 2 * waves)
+        tile >>= 1;
+    uint64_t tiles = 0;
+    const uint64_t tile_blocks = tile / 16;
+    for (const BatchDesc &r : recs)
+        tiles += ((r.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
     // Sixteen waves per workgroup each claim tiles; no more workgroups than
     // can find work.
     uint64_t grid = (tiles + 15) / 16;
@@ -78,8 +87,8 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
         grid = 1;
     if (grid > static_cast<uint64_t>(e->num_cus))
         grid = e->num_cus;
-    int rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), e->tile_bytes,
-                                    static_cast<int>(grid), 1, false);
+    int rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), static_cast<int>(tile),
+                                    static_cast<int>(grid), 2, false);
     if (rc != AES_OK)
         return rc;
     if (hipEventRecord(e->events[s], e->streams[s]) != hipSuccess) {
