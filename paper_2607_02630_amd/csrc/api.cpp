@@ -101,18 +101,25 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         sh.copies = te.copies;
         sh.grid = te.grid_per_cu * di.num_cus;
     } else if (sh.variant == AES_VARIANT_TTABLE) {
-        // Measured on MI355X (one workgroup per CU, 32-copy table): small
-        // messages prefer 512-thread workgroups with one block per lane; from
-        // 4 MiB two blocks per lane keep every workgroup busy; from 64 MiB on
-        // four blocks per lane (a 64 KiB chunk per workgroup) are fastest.
+        // One workgroup per CU with the 32-copy table.  The chunk a
+        // workgroup takes per step (workgroup size x blocks per lane) is the
+        // largest that still gives every CU at least one: a larger chunk
+        // leaves CUs idle (4 MiB with 2048-block chunks runs at half the
+        // speed of 2 MiB), a smaller one adds steps.  Measured on MI355X: 512
+        // threads x 1 block up to 2 MiB, 1024 x 1 at 4 MiB, 1024 x 2 at 8-16
+        // MiB, 1024 x 4 from 64 MiB (two blocks per lane are within 3% at 16
+        // MiB, four within 7% at 64 MiB, for either key size).
         sh.grid = di.num_cus;
         sh.copies = 32;
-        if (len <= (2u << 20)) {
-            sh.bpl = 1; sh.wg = 512;
-        } else if (len < (64u << 20)) {
-            sh.bpl = 2; sh.wg = 1024;
-        } else {
+        const uint64_t per_cu = (len / 16) / static_cast<uint64_t>(di.num_cus > 0 ? di.num_cus : 1);
+        if (per_cu >= 8192) {
             sh.bpl = 4; sh.wg = 1024;
+        } else if (per_cu >= 2048) {
+            sh.bpl = 2; sh.wg = 1024;
+        } else if (per_cu >= 1024) {
+            sh.bpl = 1; sh.wg = 1024;
+        } else {
+            sh.bpl = 1; sh.wg = 512;
         }
     } else {
         sh.bpl = 1;

@@ -74,17 +74,22 @@ def test_sweep_full_size_digest(bits, size):
     assert sha256(got) == golden()["sweep"][f"{bits}/{size}"]
 
 
+@pytest.mark.parametrize("ctr0", [0xFFFFF000, 0xFFFFF0F7], ids=["aligned", "midgroup"])
 @pytest.mark.parametrize("kw", SHAPES, ids=shape_id)
 @pytest.mark.parametrize("klen", [16, 32])
-def test_launch_shapes_match_oracle(kw, klen):
+def test_launch_shapes_match_oracle(kw, klen, ctr0):
+    """Every launch shape, on a message of many chunks with a ragged tail
+    whose counter wraps mod 2^32.  The mid-group start counter makes each
+    workgroup chunk begin inside a 256-counter group, so a 4096-block chunk
+    touches the most groups (17)."""
     g = np.random.default_rng(7 + klen)
     key, nonce = g.bytes(klen), g.bytes(12)
-    data = W.payload(g, (1 << 19) + 16 * 37 + 5)     # many chunks + ragged tail
-    ref = oracle.ctr(key, nonce, 0xFFFFF000, data, threads=0)
-    log(f"shape {shape_id(kw)} AES-{8 * klen}")
+    data = W.payload(g, (1 << 19) + 16 * 37 + 5)
+    ref = oracle.ctr(key, nonce, ctr0, data, threads=0)
+    log(f"shape {shape_id(kw)} AES-{8 * klen} ctr0 {ctr0:#x}")
     for grid in (0, 3):     # tuned grid, and a tiny grid that loops many times
         cfg = lib().launch_cfg(grid=grid, **kw)
-        got = gpu_crypt(key, nonce, 0xFFFFF000, data, cfg=cfg)
+        got = gpu_crypt(key, nonce, ctr0, data, cfg=cfg)
         assert np.array_equal(got, ref), (kw, grid)
 
 
