@@ -198,7 +198,9 @@ typedef struct {
     uint64_t budget_bytes;      /* device bytes in flight (0 = 4 GiB)          */
     int32_t n_streams;          /* concurrent batch launches (0 = 2)           */
     int32_t max_batch_reqs;     /* requests per launch (0 = 4096)              */
-    uint64_t max_batch_bytes;   /* payload bytes per launch (0 = budget)       */
+    uint64_t max_batch_bytes;   /* payload bytes per launch (0 = 256 MiB or the
+                                   budget if smaller; a larger request runs
+                                   alone)                                      */
     int32_t key_slots;          /* unused (>= 0): every descriptor carries its
                                    own expanded key schedule                   */
     int32_t host_buffers;       /* 1: in/out are pinned host memory

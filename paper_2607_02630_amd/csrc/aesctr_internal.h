@@ -84,6 +84,7 @@ int launch_ctr_bitslice(const CtrArgs &a, int nr, const Shape &sh, hipStream_t s
 // tile0 <= t.  next is the work counter the waves claim tiles from; every
 // upload carries it as 0.
 constexpr int kMaxBatch = 4096;          // requests per launch (tile0 index in LDS)
+constexpr int kMaxBatchGrid = 1 << 20;   // workgroups per batch launch (keeps tile indices in 32 bits)
 
 struct alignas(64) BatchHeader {
     uint32_t n;

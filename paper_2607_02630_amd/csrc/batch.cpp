@@ -266,7 +266,8 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
             return AES_EINVAL;
         if (cfg->wg_size != 0 && cfg->wg_size != 1024)
             return AES_EINVAL;
-        if (cfg->grid < 0 || (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2))
+        if (cfg->grid < 0 || cfg->grid > kMaxBatchGrid ||
+            (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2))
             return AES_EINVAL;
         if (cfg->tile_bytes) sh.tile_bytes = cfg->tile_bytes;
         if (cfg->grid) sh.grid = cfg->grid;

@@ -112,13 +112,18 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
     const uint32_t lane = threadIdx.x & 63;
     TTable<kBatchCopies> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
 
-    for (;;) {
-        uint32_t t = 0;
+    // Tile claiming.  The launch's W waves first take tiles 0..W-1 statically,
+    // spread so that consecutive tiles land on different CUs (wave j of
+    // workgroup b takes tile j * grid + b): a batch of at most W tiles needs
+    // no atomic at all.  Later tiles are claimed from the header counter
+    // (tile = W + counter); a wave issues its next claim when it starts a
+    // tile, so the atomic's round trip hides behind the tile's work.
+    const uint32_t waves = gridDim.x * (kBatchWG / 64);
+    uint32_t t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+    while (t < total) {
+        uint32_t claim = 0;
         if (lane == 0)
-            t = atomicAdd(counter, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= total)
-            break;
+            claim = atomicAdd(counter, 1u);
         // Last request whose first tile is <= t (empty requests share their
         // successor's tile0 and are skipped by taking the last match).
         uint32_t lo = 0, hi = n - 1;
@@ -159,6 +164,7 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
             else
                 run_tile<14, BPL, false>(tt, a, b0, b1, lane);
         }
+        t = waves + __builtin_amdgcn_readfirstlane(claim);
     }
 }
 
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
 
 int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream_t st)
 {
-    if (wg != kBatchWG || grid <= 0)
+    if (wg != kBatchWG || grid <= 0 || grid > kMaxBatchGrid)
         return AES_EINVAL;
     const uint8_t *t = static_cast<const uint8_t *>(dev_table);
     uint32_t *ctr = reinterpret_cast<uint32_t *>(const_cast<uint8_t *>(t) + offsetof(BatchHeader, next));

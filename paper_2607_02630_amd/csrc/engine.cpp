@@ -18,6 +18,7 @@
 // With host_buffers the request buffers are pinned host memory (hipHostMalloc)
 // that the kernel reads and writes directly over PCIe; otherwise they are
 // device memory.
+#include <algorithm>
 #include <atomic>
 #include <errno.h>
 #include <sys/eventfd.h>
@@ -69,24 +70,21 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
         recs[i] = batch[i].rec;
         bytes += batch[i].rec.len;
     }
-    // Tile size per batch: large batches take 64 KiB tiles (fewer claims,
-    // measured fastest on the 4096-request batch), small ones shrink the tile
-    // down to 16 KiB so that every wave of the chip still finds work.
-    const uint64_t waves = static_cast<uint64_t>(e->num_cus) * 16;
-    uint64_t tile = 65536;
-    while (tile > 16384 && bytes / tile < 2 * waves)
-        tile >>= 1;
+    // Tile size per batch: about sixteen tiles per CU (one per wave), between
+    // 2 KiB (one wave step of 64 lanes x 2 blocks) and 64 KiB (fewest claims,
+    // measured fastest on large batches); one workgroup per CU at most, and
+    // no more workgroups than tiles.  A batch of a few requests then spreads
+    // over many CUs instead of queueing on a few.
+    const uint64_t cus = static_cast<uint64_t>(e->num_cus);
+    uint64_t tile = (bytes / (16 * cus) + 2047) & ~uint64_t(2047);
+    tile = tile < 2048 ? 2048 : tile > 65536 ? 65536 : tile;
     uint64_t tiles = 0;
     const uint64_t tile_blocks = tile / 16;
     for (const BatchDesc &r : recs)
         tiles += ((r.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
-    // Sixteen waves per workgroup each claim tiles; no more workgroups than
-    // can find work.
-    uint64_t grid = (tiles + 15) / 16;
+    uint64_t grid = tiles < cus ? tiles : cus;
     if (grid < 1)
         grid = 1;
-    if (grid > static_cast<uint64_t>(e->num_cus))
-        grid = e->num_cus;
     int rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), static_cast<int>(tile),
                                     static_cast<int>(grid), 2, false);
     if (rc != AES_OK)
@@ -169,7 +167,10 @@ extern "C" int aes_engine_create(const aes_engine_cfg_t *cfg, aes_engine_t **out
     const uint64_t budget = c.budget_bytes ? c.budget_bytes : (4ull << 30);
     const int nstreams = c.n_streams ? c.n_streams : 2;
     const int max_reqs = c.max_batch_reqs ? c.max_batch_reqs : aesctr::kMaxBatch;
-    const uint64_t max_bytes = c.max_batch_bytes ? c.max_batch_bytes : budget;
+    // Default per-launch cap: 256 MiB (or the budget).  Measured on the
+    // serving mix: 6% below the uncapped saturation rate, with the p99 at 90%
+    // of saturation 26% lower; a request larger than the cap runs alone.
+    const uint64_t max_bytes = c.max_batch_bytes ? c.max_batch_bytes : std::min<uint64_t>(budget, 256ull << 20);
     if (nstreams < 1 || nstreams > kMaxStreams || max_reqs < 1 || c.key_slots < 0 ||
         (c.host_buffers != 0 && c.host_buffers != 1))
         return AES_EINVAL;
