@@ -136,6 +136,32 @@ def make_desc_array(reqs) -> ctypes.Array:
     return arr
 
 
+def make_sha_desc_array(items) -> ctypes.Array:
+    """Descriptor array for sha256_batch from (input, length, digest) triples;
+    input and digest are device tensors or raw device addresses."""
+    items = list(items)
+    arr = (N.sha256_desc_t * max(len(items), 1))()
+    for i, (x, length, digest) in enumerate(items):
+        arr[i].in_ = _addr(x)
+        arr[i].len = int(length)
+        arr[i].digest = _addr(digest)
+        arr[i].reserved = 0
+    return arr
+
+
+def sha256_batch(items=None, stream=None, descs=None, n: int | None = None) -> None:
+    """SHA-256 of many messages in one launch (asynchronous on ``stream``).
+
+    ``items``: (input, length, digest) triples (see make_sha_desc_array), or a
+    prebuilt ``descs`` array with its count ``n``."""
+    if descs is None:
+        items = list(items)
+        descs, n = make_sha_desc_array(items), len(items)
+    elif n is None:
+        raise ValueError("n is required with descs")
+    _check(lib.sha256_batch(descs, n, _stream(stream)), "sha256_batch")
+
+
 def aes_ctr_crypt_batch(reqs, stream=None, cfg: aes_batch_cfg_t | None = None, descs=None) -> None:
     """Encrypt every request with one persistent launch (asynchronous).
 

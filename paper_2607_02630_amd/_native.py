@@ -45,6 +45,11 @@ class aes_ctr_desc_t(ctypes.Structure):
                 ("ctr0", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class sha256_desc_t(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("len", ctypes.c_uint64), ("digest", ctypes.c_void_p),
+                ("reserved", ctypes.c_uint64)]
+
+
 class aes_batch_cfg_t(ctypes.Structure):
     _fields_ = [("tile_bytes", ctypes.c_int32), ("wg_size", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("blocks_per_lane", ctypes.c_int32),
@@ -96,6 +101,7 @@ SIGNATURES = {
     "aes_engine_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aes_stats_t)]),
     "aes_engine_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "aes_engine_completion_fd": (ctypes.c_int, [ctypes.c_void_p]),
+    "sha256_batch": (ctypes.c_int, [ctypes.POINTER(sha256_desc_t), ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 

@@ -1,0 +1,24 @@
+// shabatch_internal.h -- shared between the batched SHA-256 host code and its
+// kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aesctr_internal.h"
+
+namespace aesctr {
+
+// One message as the kernel sees it (device addresses).
+struct ShaRecord {
+    uint64_t in;
+    uint64_t len;
+    uint64_t digest;
+    uint64_t pad;
+};
+
+constexpr uint32_t kMaxShaBatch = 1u << 18;   // records per launch (8 MiB table)
+
+int launch_sha256_batch(const ShaRecord *dev_recs, uint32_t n, int grid, hipStream_t st);
+
+}  // namespace aesctr

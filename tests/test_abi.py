@@ -22,9 +22,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions() -> list[str]:
-    text = open(os.path.join(ROOT, "include", "aesctr.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(aes_\w+)\s*\(", text)))
+    """Every function declared by the library's headers (aesctr.h, shabatch.h)."""
+    names = set()
+    for hdr, prefix in (("aesctr.h", "aes_"), ("shabatch.h", "sha256_")):
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(" + prefix + r"\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_every_declared_function_is_exported():
@@ -134,3 +138,37 @@ def test_engine_entry_points_reject_null_handles():
     assert L.aes_engine_create(None, ctypes.byref(h)) in (N.AES_EDEVICE, N.AES_OK)
     if h.value:
         L.aes_engine_destroy(h)
+
+
+def test_sha_header_functions_are_exported_and_bound():
+    text = open(os.path.join(ROOT, "include", "shabatch.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(sha256_\w+)\s*\(", text)))
+    assert names == ["sha256_batch"]
+    L = ctypes.CDLL(N.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name)
+        assert name in N.SIGNATURES
+
+
+def test_sha_validation_before_device():
+    arr = (N.sha256_desc_t * 2)()
+    L = A.lib
+    assert L.sha256_batch(None, 0, None) == N.AES_OK
+    assert L.sha256_batch(None, 1, None) == N.AES_EINVAL
+    arr[0].in_, arr[0].len, arr[0].digest = 0x1000, 16, None
+    assert L.sha256_batch(arr, 1, None) == N.AES_EINVAL          # no digest buffer
+    arr[0].digest = 0x1008
+    assert L.sha256_batch(arr, 1, None) == N.AES_EOVERLAP        # digest inside its input
+    arr[0].digest = 0x0ff0
+    assert L.sha256_batch(arr, 1, None) == N.AES_EOVERLAP        # digest runs into its input
+    arr[0].digest, arr[0].reserved = 0x9000, 1
+    assert L.sha256_batch(arr, 1, None) == N.AES_EINVAL
+    arr[0].reserved, arr[0].len = 0, 1 << 61
+    assert L.sha256_batch(arr, 1, None) == N.AES_ERANGE          # bit length would overflow
+    arr[0].len, arr[0].in_ = 5, None
+    assert L.sha256_batch(arr, 1, None) == N.AES_EINVAL
+    # The second descriptor is checked too.
+    arr[0].in_ = 0x1000
+    arr[1].in_, arr[1].len, arr[1].digest, arr[1].reserved = 0x2000, 8, 0x3000, 7
+    assert L.sha256_batch(arr, 2, None) == N.AES_EINVAL

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the AES-CTR workloads.
+"""Seeded synthetic inputs for the AES-CTR and batched SHA-256 workloads.
 
 This module only draws random bytes and sizes; it holds none of the cipher's
 arithmetic, so both the GPU path's tests and the CPU oracle can consume the
@@ -16,8 +16,10 @@ Workloads (payloads are uniform random bytes; sizes in binary KiB/MiB):
 * ``serving``  open-loop Poisson arrivals (exponential gaps) with sizes
                70% 64 KiB / 25% 1 MiB / 5% 8 MiB, AES-128 key, nonce and
                start counter per request.
+* ``hash``     262,144 messages of 4 KiB (1 GiB) of uniform random bytes,
+               generated on the GPU with seed 2607 * 10 + 7.
 
-Seeds: master 2607, workload k uses 2607 * 10 + k (k = 1..5).
+Seeds: master 2607, workload k uses 2607 * 10 + k (k = 1..5, 7).
 """
 from __future__ import annotations
 
@@ -31,6 +33,9 @@ KiB = 1024
 MiB = 1024 * 1024
 SWEEP_SIZES = [4 * KiB << i for i in range(12)]      # 4 KiB .. 8 MiB
 BIG_SIZE = 256 * MiB
+# Batched hashing: many independent messages of one size (1 GiB in all).
+HASH_MESSAGES = 262144
+HASH_MESSAGE_BYTES = 4 * KiB
 
 
 def seed_for(k: int) -> int:
