@@ -521,13 +521,6 @@ def hash_leg(torch, A, W, with_cpu=True, reps=5):
         el = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(done / el / 1e9, 4), "unit": "GB/s", "cores": used, "kind": "oracle",
                                "sample": f"4096 x 4 KiB messages through the multithreaded oracle ({el:.1f} s)"}
-        from concurrent.futures import ThreadPoolExecutor
-        rows = [sample[i].tobytes() for i in range(sample.shape[0])]
-        with ThreadPoolExecutor(threads) as ex:
-            t0 = time.perf_counter()
-            list(ex.map(lambda m: hashlib.sha256(m).digest(), rows * 8))
-            el = time.perf_counter() - t0
-        out["hashlib_context_gbps"] = round(8 * sample.nbytes / el / 1e9, 3)
     del src, dig
     torch.cuda.empty_cache()
     return out

@@ -76,12 +76,13 @@ def test_unaligned_inputs_and_digests(in_align, dig_align):
 
 
 def test_more_messages_than_one_launch():
-    """70,000 messages exceed one launch's table (65,536): the call splits."""
+    """267,144 messages exceed one launch's table (262,144): the call splits
+    into two launches, each with its own length order."""
     g = np.random.default_rng(3)
-    n = 70000
+    n = (1 << 18) + 5000
     lens = g.integers(0, 200, size=n)
     msgs = [g.bytes(int(k)) for k in lens]
-    log("sha256 70000 messages")
+    log(f"sha256 {n} messages")
     got = gpu_hash(msgs)
     for i in range(n):
         assert got[i] == sha.sha256(msgs[i]), i
