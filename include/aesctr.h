@@ -160,9 +160,9 @@ typedef struct {
 int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream);
 
 /* Batch launch shape: tile_bytes (bytes of a request one wave-tile covers,
- * multiple of 1024), wg_size, grid, blocks_per_lane; zero = default (64 KiB
- * tiles, 2 blocks per lane, 1024-thread workgroups, one per CU, unless a
- * tune cache says otherwise).  use_graph: 1 = captured graph, 0 = plain copy
+ * multiple of 1024), wg_size, grid, blocks_per_lane; zero = default (tiles
+ * sized to the batch, about sixteen per CU within 2-64 KiB; 2 blocks per
+ * lane; 1024-thread workgroups, one per CU; a tune cache may override).  use_graph: 1 = captured graph, 0 = plain copy
  * + launch; a call without cfg uses the graph. */
 typedef struct {
     int32_t tile_bytes;

@@ -112,6 +112,8 @@ int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream
 // number of records (kMaxBatch per launch) on the (device, stream) context and
 // launches them, through the per-slot captured graph or a plain copy+launch.
 int check_desc(const aes_ctr_desc_t &d);
+// Tile size for a batch of batch_bytes payload bytes (2-64 KiB, multiple of 2 KiB).
+uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus);
 void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o);
 int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
                    int bpl, bool use_graph);

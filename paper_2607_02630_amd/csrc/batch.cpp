@@ -161,6 +161,18 @@ size_t stage(uint8_t *buf, const BatchDesc *recs, size_t n, uint32_t tile_blocks
 
 }  // namespace
 
+uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus)
+{
+    // About sixteen tiles per CU (one per wave of a workgroup), between 2 KiB
+    // (one wave step: 64 lanes x 2 blocks) and 64 KiB.  Measured on MI355X:
+    // on the 4096-request workload 64 KiB tiles (3.59 ms) beat 16 KiB (3.67)
+    // and 4 KiB (12.8, when every tile was claimed with an atomic); small
+    // batches need small tiles to reach many CUs.
+    const uint64_t cus = static_cast<uint64_t>(num_cus > 0 ? num_cus : 1);
+    uint64_t tile = (batch_bytes / (16 * cus) + 2047) & ~uint64_t(2047);
+    return tile < 2048 ? 2048 : tile > 65536 ? 65536 : tile;
+}
+
 void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o)
 {
     KeyMaterial km;
@@ -252,9 +264,8 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
         if (rc != AES_OK)
             return rc;
     }
-    // Measured on MI355X over the 4096-request workload: 64 KiB tiles with two
-    // blocks per lane (3.59 ms) beat 16 KiB (3.67 ms) and 4 KiB (12.8 ms).
-    BatchShape sh{65536, 1024, 0, 2, 1};
+    // Tile size 0 = sized to the batch (batch_tile_bytes); two blocks per lane.
+    BatchShape sh{0, 1024, 0, 2, 1};
     TuneEntry te;
     if (tune_lookup_batch(&te)) {
         sh.bpl = te.bpl <= 2 ? te.bpl : 1;
@@ -290,6 +301,12 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
     if (cs != hipStreamCaptureStatusNone)
         return AES_EINVAL;
 
+    if (sh.tile_bytes == 0) {
+        uint64_t bytes = 0;
+        for (size_t i = 0; i < n; ++i)
+            bytes += desc[i].len;
+        sh.tile_bytes = static_cast<int>(batch_tile_bytes(bytes, di.num_cus));
+    }
     thread_local std::vector<BatchDesc> recs;
     recs.resize(n);
     for (size_t i = 0; i < n; ++i)

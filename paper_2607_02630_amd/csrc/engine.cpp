@@ -70,14 +70,11 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
         recs[i] = batch[i].rec;
         bytes += batch[i].rec.len;
     }
-    // Tile size per batch: about sixteen tiles per CU (one per wave), between
-    // 2 KiB (one wave step of 64 lanes x 2 blocks) and 64 KiB (fewest claims,
-    // measured fastest on large batches); one workgroup per CU at most, and
-    // no more workgroups than tiles.  A batch of a few requests then spreads
-    // over many CUs instead of queueing on a few.
+    // Tile size sized to the batch (see batch_tile_bytes); one workgroup per
+    // CU at most, and no more workgroups than tiles, so a batch of a few
+    // requests spreads over many CUs and leaves the rest to the other stream.
     const uint64_t cus = static_cast<uint64_t>(e->num_cus);
-    uint64_t tile = (bytes / (16 * cus) + 2047) & ~uint64_t(2047);
-    tile = tile < 2048 ? 2048 : tile > 65536 ? 65536 : tile;
+    const uint64_t tile = aesctr::batch_tile_bytes(bytes, e->num_cus);
     uint64_t tiles = 0;
     const uint64_t tile_blocks = tile / 16;
     for (const BatchDesc &r : recs)
