@@ -128,6 +128,15 @@ int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[12], uint32_
                       const void *in, void *out, size_t len,
                       const aes_launch_cfg_t *cfg, void *stream);
 
+/* The launch shape aes_ctr_crypt_cfg would use for a len-byte message with
+ * this key size and cfg (NULL = defaults): the default shape, or the tune
+ * cache's entry for the nearest size, overridden by cfg's non-zero fields,
+ * with the grid clamped to the work.  All fields of *out are set (variant 1
+ * or 2, never AUTO; lds_copies 0 for the bitsliced kernel).  Host only; it
+ * needs the current device's CU count.  Errors: AES_EINVAL (null out, key
+ * size not 128/256, bad cfg), AES_EDEVICE. */
+int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_cfg_t *cfg, aes_launch_cfg_t *out);
+
 /* ---------------------------------------------------------------------- */
 /* Batch: many requests, one launch                                        */
 /* ---------------------------------------------------------------------- */

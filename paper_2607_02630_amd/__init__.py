@@ -136,6 +136,15 @@ def make_desc_array(reqs) -> ctypes.Array:
     return arr
 
 
+def launch_shape(key_bits: int, length: int, cfg: aes_launch_cfg_t | None = None) -> dict:
+    """The launch shape aes_ctr_crypt would use (aes_ctr_launch_shape)."""
+    out = aes_launch_cfg_t()
+    _check(lib.aes_ctr_launch_shape(key_bits, length, ctypes.byref(cfg) if cfg is not None else None,
+                                    ctypes.byref(out)), "aes_ctr_launch_shape")
+    return {"variant": out.variant, "blocks_per_lane": out.blocks_per_lane, "wg_size": out.wg_size,
+            "grid": out.grid, "lds_copies": out.lds_copies}
+
+
 def make_sha_desc_array(items) -> ctypes.Array:
     """Descriptor array for sha256_batch from (input, length, digest) triples;
     input and digest are device tensors or raw device addresses."""

@@ -101,6 +101,8 @@ SIGNATURES = {
     "aes_engine_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aes_stats_t)]),
     "aes_engine_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "aes_engine_completion_fd": (ctypes.c_int, [ctypes.c_void_p]),
+    "aes_ctr_launch_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(aes_launch_cfg_t),
+                                            ctypes.POINTER(aes_launch_cfg_t)]),
     "sha256_batch": (ctypes.c_int, [ctypes.POINTER(sha256_desc_t), ctypes.c_size_t, ctypes.c_void_p]),
 }
 

@@ -10,7 +10,7 @@ graph over buffers larger than the Infinity Cache.  The fastest shape per
 (AESCTR_TUNE_CACHE or tune_cache.json next to the library).  The batch
 kernel's tile size and blocks per lane are tuned on the 4096-request batch.
 
-Usage: python -m paper_2607_02630_amd.autotune [--quick] [--out PATH]
+Usage: python -m paper_2607_02630_amd.autotune [--quick] [--sizes B,B,...] [--no-batch] [--out PATH]
 """
 from __future__ import annotations
 
@@ -62,6 +62,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="fewer sizes and shapes")
     ap.add_argument("--out", default=os.path.join(HERE, "tune_cache.json"))
+    ap.add_argument("--sizes", default="", help="comma-separated sweep sizes in bytes (default: all)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch-kernel tile search")
     args = ap.parse_args(argv)
     sys.path.insert(0, ROOT)
     import torch
@@ -71,6 +73,11 @@ def main(argv=None):
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     gold = _golden()
     sizes = [64 * 1024, MiB, 8 * MiB, W.BIG_SIZE] if args.quick else W.SWEEP_SIZES + [W.BIG_SIZE]
+    if args.sizes:
+        sizes = [int(x) for x in args.sizes.split(",")]
+        unknown = [x for x in sizes if f"128/{x}" not in gold]
+        if unknown:
+            raise SystemExit(f"no stored digests for sizes {unknown}")
     entries, report = [], []
     for bits in (128, 256):
         key, nonce = W.sweep_key(bits)
@@ -106,7 +113,8 @@ def main(argv=None):
                 print(json.dumps(report[-1]), flush=True)
             del ins, outs, src
             torch.cuda.empty_cache()
-    entries.append(tune_batch(torch, A, W, cus))
+    if not args.no_batch:
+        entries.append(tune_batch(torch, A, W, cus))
     with open(args.out, "w") as f:
         json.dump({"generated": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries,
                    "measured": report}, f, indent=1)

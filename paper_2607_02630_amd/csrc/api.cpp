@@ -173,6 +173,63 @@ extern "C" const char *aes_strerror(int status)
     }
 }
 
+namespace {
+
+int check_cfg(const aes_launch_cfg_t *cfg, int *variant)
+{
+    *variant = cfg ? cfg->variant : AES_VARIANT_AUTO;
+    if (*variant < AES_VARIANT_AUTO || *variant > AES_VARIANT_BITSLICE)
+        return AES_EINVAL;
+    if (cfg) {
+        if (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2 &&
+            cfg->blocks_per_lane != 4)
+            return AES_EINVAL;
+        if (cfg->wg_size != 0 && (cfg->wg_size < 64 || cfg->wg_size > 1024 || cfg->wg_size % 64 != 0))
+            return AES_EINVAL;
+        if (cfg->grid < 0 || (cfg->lds_copies != 0 && cfg->lds_copies != 32 && cfg->lds_copies != 64))
+            return AES_EINVAL;
+    }
+    return AES_OK;
+}
+
+// The launch shape for len bytes: the default (or tuned) shape, overridden
+// by the non-zero fields of cfg, with the grid clamped to the work.
+Shape resolve_shape(int variant, int key_bits, uint64_t len, const aes_launch_cfg_t *cfg, const DeviceInfo &di)
+{
+    Shape sh = default_shape(variant, key_bits, len, di);
+    if (cfg) {
+        if (cfg->blocks_per_lane) sh.bpl = cfg->blocks_per_lane;
+        if (cfg->wg_size) sh.wg = cfg->wg_size;
+        if (cfg->grid) sh.grid = cfg->grid;
+        if (cfg->lds_copies) sh.copies = cfg->lds_copies;
+    }
+    clamp_grid(&sh, len);
+    return sh;
+}
+
+}  // namespace
+
+extern "C" int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_cfg_t *cfg, aes_launch_cfg_t *out)
+{
+    if (!out || (key_bits != 128 && key_bits != 256))
+        return AES_EINVAL;
+    int variant;
+    int rc = check_cfg(cfg, &variant);
+    if (rc != AES_OK)
+        return rc;
+    DeviceInfo di;
+    if ((rc = device_info(&di)) != AES_OK)
+        return rc;
+    const Shape sh = resolve_shape(variant, key_bits, len ? len : 1, cfg, di);
+    *out = aes_launch_cfg_t{};
+    out->variant = sh.variant;
+    out->blocks_per_lane = sh.bpl;
+    out->wg_size = sh.wg;
+    out->grid = sh.grid;
+    out->lds_copies = sh.copies;
+    return AES_OK;
+}
+
 extern "C" int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[12], uint32_t ctr0,
                                  const void *in, void *out, size_t len, const aes_launch_cfg_t *cfg,
                                  void *stream)
@@ -184,32 +241,16 @@ extern "C" int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[1
         return AES_EINVAL;
     if ((rc = check_buffers(in, out, len)) != AES_OK)
         return rc;
-    int variant = cfg ? cfg->variant : AES_VARIANT_AUTO;
-    if (variant < AES_VARIANT_AUTO || variant > AES_VARIANT_BITSLICE)
-        return AES_EINVAL;
-    if (cfg) {
-        if (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2 &&
-            cfg->blocks_per_lane != 4)
-            return AES_EINVAL;
-        if (cfg->wg_size != 0 && (cfg->wg_size < 64 || cfg->wg_size > 1024 || cfg->wg_size % 64 != 0))
-            return AES_EINVAL;
-        if (cfg->grid < 0 || (cfg->lds_copies != 0 && cfg->lds_copies != 32 && cfg->lds_copies != 64))
-            return AES_EINVAL;
-    }
+    int variant;
+    if ((rc = check_cfg(cfg, &variant)) != AES_OK)
+        return rc;
     if (len == 0)
         return AES_OK;
 
     DeviceInfo di;
     if ((rc = device_info(&di)) != AES_OK)
         return rc;
-    Shape sh = default_shape(variant, sched->key_bits, len, di);
-    if (cfg) {
-        if (cfg->blocks_per_lane) sh.bpl = cfg->blocks_per_lane;
-        if (cfg->wg_size) sh.wg = cfg->wg_size;
-        if (cfg->grid) sh.grid = cfg->grid;
-        if (cfg->lds_copies) sh.copies = cfg->lds_copies;
-    }
-    clamp_grid(&sh, len);
+    const Shape sh = resolve_shape(variant, sched->key_bits, len, cfg, di);
 
     KeyMaterial km;
     make_key_material(*sched, nonce, &km);

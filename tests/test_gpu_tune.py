@@ -1,0 +1,71 @@
+"""The autotuner and its cache (GPU).
+
+The autotuner times only candidates whose output digest equals the one the
+oracle wrote (tests/golden/ctr_digests.json) and exits non-zero otherwise.
+This test runs it on two sizes in a subprocess, then, in a fresh process
+pointed at the written cache (AESCTR_TUNE_CACHE), checks the round trip:
+aes_ctr_launch_shape returns each cached shape for its size, and
+aes_ctr_crypt with that shape still reproduces the stored digest.
+"""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SIZES = [65536, 1048576]
+
+CHECK = r"""
+import hashlib, json, sys
+import torch
+import paper_2607_02630_amd as A
+import workloads as W
+cache = json.load(open(sys.argv[1]))
+gold = json.load(open("tests/golden/ctr_digests.json"))["sweep"]
+cus = torch.cuda.get_device_properties(0).multi_processor_count
+checked = 0
+for e in cache["entries"]:
+    if e["variant"] not in (1, 2):
+        continue
+    size, bits = 1 << e["size_log2"], e["key_bits"]
+    shape = A.launch_shape(bits, size, A.launch_cfg(variant=e["variant"]))
+    assert shape["variant"] == e["variant"], (e, shape)
+    assert shape["blocks_per_lane"] == e["bpl"] and shape["wg_size"] == e["wg"], (e, shape)
+    if e["variant"] == 1:
+        assert shape["lds_copies"] == e["copies"], (e, shape)
+    assert shape["grid"] <= e["grid_per_cu"] * cus, (e, shape)
+    key, nonce = W.sweep_key(bits)
+    x = torch.from_numpy(W.sweep_payload(size, bits)).cuda()
+    y = A.aes_ctr_crypt(A.aes_expand_key(key), nonce, 1, x, cfg=A.launch_cfg(variant=e["variant"]))
+    torch.cuda.synchronize()
+    assert hashlib.sha256(y.cpu().numpy().tobytes()).hexdigest() == gold[f"{bits}/{size}"], e
+    checked += 1
+print("checked", checked)
+"""
+
+
+def test_autotune_writes_a_cache_the_library_uses(tmp_path):
+    out = tmp_path / "tune_cache.json"
+    env = dict(os.environ)
+    env.pop("AESCTR_TUNE_CACHE", None)
+    r = subprocess.run([sys.executable, "-m", "paper_2607_02630_amd.autotune", "--sizes",
+                        ",".join(map(str, SIZES)), "--no-batch", "--out", str(out)],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    cache = json.loads(out.read_text())
+    have = {(e["variant"], e["key_bits"], e["size_log2"]) for e in cache["entries"]}
+    for v in (1, 2):
+        for bits in (128, 256):
+            for size in SIZES:
+                assert (v, bits, size.bit_length() - 1) in have
+    env["AESCTR_TUNE_CACHE"] = str(out)
+    r = subprocess.run([sys.executable, "-c", CHECK, str(out)], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "checked 8" in r.stdout

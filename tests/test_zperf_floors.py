@@ -1,0 +1,84 @@
+"""Performance floors on the GPU, so a regression fails loudly.
+
+Floors sit well below the measured MI355X figures (recorded beside each) so
+that box-to-box variation does not fail them, while a broken fast path
+(a fallback, a serialised launch, a shape that leaves CUs idle) does.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import bench as B
+    import paper_2607_02630_amd as A
+    import workloads as W
+    return torch, B, A, W
+
+
+@pytest.mark.parametrize("size,floor", [(8 * MiB, 700.0), (256 * MiB, 1100.0)])
+def test_single_buffer_floor(env, size, floor):
+    """AES-128-CTR steady state over cold buffers (measured: 1028 / 1455-1549 GB/s)."""
+    torch, B, A, W = env
+    key, nonce = W.sweep_key(128)
+    sched = A.aes_expand_key(key)
+    _, ins, outs = B.make_buffers(torch, W, size, 128)
+    steps = max(20, min(1000, int(8e9 / size)))
+    t, _ = B.steady_state(torch, A, sched, nonce, ins, outs, steps, 10)
+    gbs = size * steps / (t.ms * 1e-3) / 1e9
+    del ins, outs
+    torch.cuda.empty_cache()
+    assert gbs >= floor, f"{size} B: {gbs:.1f} GB/s < floor {floor}"
+
+
+def test_batch_floor(env):
+    """4096-request batch in one call (measured: 1283 GB/s)."""
+    torch, B, A, W = env
+    reqs = W.batch_requests()
+    total = sum(r.length for r in reqs)
+    src = W.device_payload(total, W.seed_for(4))
+    dst = torch.empty_like(src)
+    objs, off = [], 0
+    for r in reqs:
+        objs.append(A.Request(A.aes_expand_key(r.key), r.nonce, r.ctr0, src.data_ptr() + off, dst.data_ptr() + off,
+                              r.length))
+        off += r.length
+    descs = A.make_desc_array(objs)
+    A.aes_ctr_crypt_batch(objs, descs=descs)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(3):
+        with B.Timer(torch) as t:
+            A.aes_ctr_crypt_batch(objs, descs=descs)
+        ms.append(t.ms)
+    gbs = total / (sorted(ms)[1] * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    assert gbs >= 900.0, f"batch: {gbs:.1f} GB/s"
+
+
+def test_sha256_batch_floor(env):
+    """262,144 x 4 KiB hashed per call (measured: 719-723 GB/s)."""
+    torch, B, A, W = env
+    n, size = W.HASH_MESSAGES, W.HASH_MESSAGE_BYTES
+    src = W.device_payload(n * size, W.seed_for(7))
+    dig = torch.zeros(n * 32, dtype=torch.uint8, device="cuda")
+    descs = A.make_sha_desc_array((src.data_ptr() + i * size, size, dig.data_ptr() + 32 * i) for i in range(n))
+    A.sha256_batch(descs=descs, n=n)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(3):
+        with B.Timer(torch) as t:
+            A.sha256_batch(descs=descs, n=n)
+        ms.append(t.ms)
+    gbs = n * size / (sorted(ms)[1] * 1e-3) / 1e9
+    del src, dig
+    torch.cuda.empty_cache()
+    assert gbs >= 450.0, f"sha256 batch: {gbs:.1f} GB/s"
