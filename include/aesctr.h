@@ -143,7 +143,12 @@ int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_cfg_t *cfg, 
 
 /* One request.  in/out are device pointers (in == out allowed), sched a host
  * pointer to its expanded key (AES-128 and AES-256 may be mixed), nonce and
- * ctr0 its counter-block parameters.  flags must be 0. */
+ * ctr0 its counter-block parameters.  flags: 0 for AES-CTR; for the engine
+ * (aes_submit) also AES_FLAG_SHA256, which makes the request a SHA-256 hash
+ * of in[0..len) into the 32-byte digest at out (shabatch.h's semantics;
+ * sched, nonce and ctr0 are ignored and sched may be NULL). */
+enum { AES_FLAG_SHA256 = 1 };
+
 typedef struct {
     const void *in;
     void *out;
@@ -239,6 +244,9 @@ int aes_engine_destroy(aes_engine_t *e);
 
 /* Submit one request (*d copied, its schedule copied).  Never blocks on the
  * device: a request that does not fit the budget now waits in FIFO order.
+ * Cipher and hash requests (flags = AES_FLAG_SHA256) may be mixed; a launch
+ * runs the batch kernel for the cipher requests and the hash kernel for the
+ * hash requests back to back on its stream.
  * Takes no lock; when 32768 requests are already queued (admitted requests
  * do not count) the call yields until the engine takes some.  Thread-safe;
  * calls racing with aes_engine_destroy are not allowed.

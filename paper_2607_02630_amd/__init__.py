@@ -1,4 +1,4 @@
-"""MI355X-native AES counter mode behind a C ABI (libaesctr.so).
+"""MI355X-native AES counter mode (and batched SHA-256) behind a C ABI (libaesctr.so).
 
 Thin Python binding with the library's own names.  Buffers are torch CUDA
 tensors (any dtype, contiguous) or raw device addresses; streams are
@@ -126,6 +126,23 @@ class Request:
         d.sched = ctypes.pointer(self.sched)
         d.nonce[:] = list(self.nonce)
         d.ctr0 = self.ctr0
+        return d
+
+
+class HashRequest:
+    """One engine request that hashes ``x`` (``length`` bytes) with SHA-256
+    into the 32-byte ``digest`` buffer (flags = AES_FLAG_SHA256)."""
+
+    def __init__(self, x, digest, length: int | None = None):
+        self.x, self.digest = x, digest
+        self.length = length if length is not None else _nbytes(x)
+
+    def desc(self) -> aes_ctr_desc_t:
+        d = aes_ctr_desc_t()
+        d.in_ = _addr(self.x) if self.length else None
+        d.out = _addr(self.digest)
+        d.len = self.length
+        d.flags = N.AES_FLAG_SHA256
         return d
 
 

@@ -23,6 +23,7 @@ AES_ETIMEDOUT = -7
 AES_EOVERLAP = -8
 AES_ECLOSED = -9
 AES_ECANCELED = -10
+AES_FLAG_SHA256 = 1
 
 AES_VARIANT_AUTO = 0
 AES_VARIANT_TTABLE = 1

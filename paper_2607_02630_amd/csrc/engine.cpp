@@ -28,6 +28,7 @@
 
 #include "aesctr_internal.h"
 #include "engine_core.h"
+#include "shabatch_internal.h"
 
 using aesctr::BatchDesc;
 using Core = aesctr::EngineCore<BatchDesc>;
@@ -62,29 +63,45 @@ void notify_fd(int fd)
     }
 }
 
-int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vector<BatchDesc> &recs)
+int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vector<BatchDesc> &recs,
+                 std::vector<aesctr::ShaRecord> &hashes)
 {
-    recs.resize(batch.size());
+    // Cipher records go to the batch kernel, hash records (nr == 0) to the
+    // hash kernel; both run on this stream before its completion event.
+    recs.clear();
+    hashes.clear();
     uint64_t bytes = 0;
-    for (size_t i = 0; i < batch.size(); ++i) {
-        recs[i] = batch[i].rec;
-        bytes += batch[i].rec.len;
+    for (const Req &q : batch) {
+        if (q.rec.nr == 0) {
+            hashes.push_back(aesctr::ShaRecord{q.rec.in, q.rec.len, q.rec.out, 0});
+        } else {
+            recs.push_back(q.rec);
+            bytes += q.rec.len;
+        }
     }
-    // Tile size sized to the batch (see batch_tile_bytes); one workgroup per
-    // CU at most, and no more workgroups than tiles, so a batch of a few
-    // requests spreads over many CUs and leaves the rest to the other stream.
-    const uint64_t cus = static_cast<uint64_t>(e->num_cus);
-    const uint64_t tile = aesctr::batch_tile_bytes(bytes, e->num_cus);
-    uint64_t tiles = 0;
-    const uint64_t tile_blocks = tile / 16;
-    for (const BatchDesc &r : recs)
-        tiles += ((r.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
-    uint64_t grid = tiles < cus ? tiles : cus;
-    if (grid < 1)
-        grid = 1;
-    int rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), static_cast<int>(tile),
+    int rc = AES_OK;
+    if (!recs.empty()) {
+        // Tile size sized to the batch (see batch_tile_bytes); one workgroup
+        // per CU at most, and no more workgroups than tiles, so a batch of a
+        // few requests spreads over many CUs and leaves the rest to the other
+        // stream.
+        const uint64_t cus = static_cast<uint64_t>(e->num_cus);
+        const uint64_t tile = aesctr::batch_tile_bytes(bytes, e->num_cus);
+        uint64_t tiles = 0;
+        const uint64_t tile_blocks = tile / 16;
+        for (const BatchDesc &r : recs)
+            tiles += ((r.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
+        uint64_t grid = tiles < cus ? tiles : cus;
+        if (grid < 1)
+            grid = 1;
+        rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), static_cast<int>(tile),
                                     static_cast<int>(grid), 2, false);
-    if (rc != AES_OK)
+        if (rc != AES_OK)
+            return rc;
+    }
+    if (!hashes.empty() &&
+        (rc = aesctr::launch_sha_records(e->device, e->streams[s], hashes.data(), hashes.size(), e->num_cus)) !=
+            AES_OK)
         return rc;
     if (hipEventRecord(e->events[s], e->streams[s]) != hipSuccess) {
         note_device_error(hipGetLastError());
@@ -104,6 +121,7 @@ void drive(aes_engine *e)
     const int ns = static_cast<int>(e->streams.size());
     std::vector<Req> batch;
     std::vector<BatchDesc> recs;
+    std::vector<aesctr::ShaRecord> hashes;
     int active = 0;
     int64_t busy_since = 0;
     for (;;) {
@@ -129,7 +147,7 @@ void drive(aes_engine *e)
                 continue;
             if (!e->core.take_batch(batch))
                 break;
-            int rc = launch_batch(e, s, batch, recs);
+            int rc = launch_batch(e, s, batch, recs, hashes);
             if (rc != AES_OK) {
                 e->core.complete(batch, rc, Core::now_ns());
                 continue;
@@ -279,10 +297,33 @@ extern "C" int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t
 {
     if (!e || !d || !ticket || t_arrival_ns < 0)
         return AES_EINVAL;
-    int rc = aesctr::check_desc(*d);
-    if (rc != AES_OK)
-        return rc;
+    int rc;
     Req r;
+    if (d->flags == AES_FLAG_SHA256) {
+        // A hash request: in = message, out = 32-byte digest.  Its record
+        // carries nr = 0, which no cipher record has.
+        if (d->reserved != 0)
+            return AES_EINVAL;
+        if ((rc = aesctr::check_sha(d->in, d->len, d->out)) != AES_OK)
+            return rc;
+        r.rec = BatchDesc{};
+        r.rec.in = reinterpret_cast<uint64_t>(d->in);
+        r.rec.out = reinterpret_cast<uint64_t>(d->out);
+        r.rec.len = d->len;
+        r.rec.nr = 0;
+        if (e->host_buffers) {
+            uint64_t din = 0, dout = 0;
+            if ((d->len > 0 && (rc = host_to_device(d->in, &din)) != AES_OK) ||
+                (rc = host_to_device(d->out, &dout)) != AES_OK)
+                return rc;
+            r.rec.in = din;
+            r.rec.out = dout;
+        }
+        r.bytes = d->len + 32;
+        return e->core.submit(std::move(r), ticket, t_arrival_ns);
+    }
+    if ((rc = aesctr::check_desc(*d)) != AES_OK)
+        return rc;
     r.bytes = d->len;
     aesctr::make_batch_record(*d, &r.rec);
     if (e->host_buffers && d->len > 0) {

@@ -67,26 +67,91 @@ ShaCtx *get_ctx(int device, void *stream, int *rc)
     return c;
 }
 
-int check(const sha256_desc_t &d)
+}  // namespace
+}  // namespace aesctr
+
+namespace aesctr {
+
+int check_sha(const void *in, uint64_t len, const void *digest)
 {
-    if (d.reserved != 0 || !d.digest)
+    if (!digest)
         return AES_EINVAL;
-    if (d.len == 0)
+    if (len == 0)
         return AES_OK;
-    if (!d.in)
+    if (!in)
         return AES_EINVAL;
-    if (d.len > (uint64_t(1) << 61) - 1)
+    if (len > (uint64_t(1) << 61) - 1)
         return AES_ERANGE;
-    const uintptr_t a = reinterpret_cast<uintptr_t>(d.in);
-    const uintptr_t b = reinterpret_cast<uintptr_t>(d.digest);
-    if (a > UINTPTR_MAX - d.len || b > UINTPTR_MAX - 32)
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in);
+    const uintptr_t b = reinterpret_cast<uintptr_t>(digest);
+    if (a > UINTPTR_MAX - len || b > UINTPTR_MAX - 32)
         return AES_EINVAL;
-    if (a < b + 32 && b < a + d.len)
+    if (a < b + 32 && b < a + len)
         return AES_EOVERLAP;
     return AES_OK;
 }
 
-}  // namespace
+int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t n, int num_cus)
+{
+    if (n == 0)
+        return AES_OK;
+    int rc;
+    ShaCtx *c = get_ctx(device, st, &rc);
+    if (!c)
+        return rc;
+
+    // Longest first, so lanes of a wave (consecutive records) hash similar
+    // lengths: a stable counting sort on the bit length of len (O(n); equal
+    // lengths keep the caller's order and skip the pass).
+    thread_local std::vector<uint32_t> order;
+    order.resize(n);
+    uint64_t lo = recs[0].len, hi = recs[0].len;
+    for (size_t i = 1; i < n; ++i) {
+        lo = std::min<uint64_t>(lo, recs[i].len);
+        hi = std::max<uint64_t>(hi, recs[i].len);
+    }
+    if (lo == hi) {
+        std::iota(order.begin(), order.end(), 0u);
+    } else {
+        auto bucket = [](uint64_t len) { return 64 - __builtin_clzll(len | 1); };   // 1..62
+        size_t start[66] = {};
+        for (size_t i = 0; i < n; ++i)
+            ++start[65 - bucket(recs[i].len)];
+        size_t acc = 0;
+        for (size_t &v : start) {
+            const size_t cnt = v;
+            v = acc;
+            acc += cnt;
+        }
+        for (size_t i = 0; i < n; ++i)
+            order[start[65 - bucket(recs[i].len)]++] = static_cast<uint32_t>(i);
+    }
+
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (size_t first = 0; first < n; first += kMaxShaBatch) {
+        const uint32_t m = static_cast<uint32_t>(std::min<size_t>(n - first, kMaxShaBatch));
+        const int slot = c->next;
+        c->next = (c->next + 1) % kShaSlots;
+        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess)
+            return device_error();
+        ShaRecord *s = c->staging[slot];
+        for (uint32_t i = 0; i < m; ++i)
+            s[i] = recs[order[first + i]];
+        if (hipMemcpyAsync(c->dev, s, sizeof(ShaRecord) * m, hipMemcpyHostToDevice, st) != hipSuccess)
+            return device_error();
+        // One lane per message; at most 16 workgroups of 256 lanes per CU,
+        // extra messages looping in grid strides.
+        const uint32_t groups = (m + 255) / 256;
+        const int grid = static_cast<int>(std::min<uint32_t>(groups, static_cast<uint32_t>(16 * num_cus)));
+        if ((rc = launch_sha256_batch(c->dev, m, grid, st)) != AES_OK)
+            return rc;
+        if (hipEventRecord(c->done[slot], st) != hipSuccess)
+            return device_error();
+        c->used[slot] = true;
+    }
+    return AES_OK;
+}
+
 }  // namespace aesctr
 
 using namespace aesctr;
@@ -98,7 +163,9 @@ extern "C" int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream)
     if (!desc)
         return AES_EINVAL;
     for (size_t i = 0; i < n; ++i) {
-        const int rc = check(desc[i]);
+        if (desc[i].reserved != 0)
+            return AES_EINVAL;
+        const int rc = check_sha(desc[i].in, desc[i].len, desc[i].digest);
         if (rc != AES_OK)
             return rc;
     }
@@ -106,61 +173,10 @@ extern "C" int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream)
     int rc = device_info(&di);
     if (rc != AES_OK)
         return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    ShaCtx *c = get_ctx(di.ordinal, stream, &rc);
-    if (!c)
-        return rc;
-
-    // Longest first, so lanes of a wave (consecutive records) hash similar
-    // lengths: a stable counting sort on the bit length of len (O(n); equal
-    // lengths keep the caller's order and skip the pass).
-    thread_local std::vector<uint32_t> order;
-    order.resize(n);
-    uint64_t lo = desc[0].len, hi = desc[0].len;
-    for (size_t i = 1; i < n; ++i) {
-        lo = std::min<uint64_t>(lo, desc[i].len);
-        hi = std::max<uint64_t>(hi, desc[i].len);
-    }
-    if (lo == hi) {
-        std::iota(order.begin(), order.end(), 0u);
-    } else {
-        auto bucket = [](uint64_t len) { return 64 - __builtin_clzll(len | 1); };   // 1..62
-        size_t start[66] = {};
-        for (size_t i = 0; i < n; ++i)
-            ++start[65 - bucket(desc[i].len)];
-        size_t acc = 0;
-        for (size_t& v : start) {
-            const size_t c = v;
-            v = acc;
-            acc += c;
-        }
-        for (size_t i = 0; i < n; ++i)
-            order[start[65 - bucket(desc[i].len)]++] = static_cast<uint32_t>(i);
-    }
-
-    std::lock_guard<std::mutex> lk(c->mu);
-    for (size_t first = 0; first < n; first += kMaxShaBatch) {
-        const uint32_t m = static_cast<uint32_t>(std::min<size_t>(n - first, kMaxShaBatch));
-        const int slot = c->next;
-        c->next = (c->next + 1) % kShaSlots;
-        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess)
-            return device_error();
-        ShaRecord *s = c->staging[slot];
-        for (uint32_t i = 0; i < m; ++i) {
-            const sha256_desc_t &d = desc[order[first + i]];
-            s[i] = ShaRecord{reinterpret_cast<uint64_t>(d.in), d.len, reinterpret_cast<uint64_t>(d.digest), 0};
-        }
-        if (hipMemcpyAsync(c->dev, s, sizeof(ShaRecord) * m, hipMemcpyHostToDevice, st) != hipSuccess)
-            return device_error();
-        // One lane per message; at most 16 workgroups of 256 lanes per CU,
-        // extra messages looping in grid strides.
-        const uint32_t groups = (m + 255) / 256;
-        const int grid = static_cast<int>(std::min<uint32_t>(groups, static_cast<uint32_t>(16 * di.num_cus)));
-        if ((rc = launch_sha256_batch(c->dev, m, grid, st)) != AES_OK)
-            return rc;
-        if (hipEventRecord(c->done[slot], st) != hipSuccess)
-            return device_error();
-        c->used[slot] = true;
-    }
-    return AES_OK;
+    thread_local std::vector<ShaRecord> recs;
+    recs.resize(n);
+    for (size_t i = 0; i < n; ++i)
+        recs[i] = ShaRecord{reinterpret_cast<uint64_t>(desc[i].in), desc[i].len,
+                            reinterpret_cast<uint64_t>(desc[i].digest), 0};
+    return launch_sha_records(di.ordinal, static_cast<hipStream_t>(stream), recs.data(), n, di.num_cus);
 }

@@ -21,4 +21,11 @@ constexpr uint32_t kMaxShaBatch = 1u << 18;   // records per launch (8 MiB table
 
 int launch_sha256_batch(const ShaRecord *dev_recs, uint32_t n, int grid, hipStream_t st);
 
+// Validation of one message (AES_OK, AES_EINVAL, AES_ERANGE, AES_EOVERLAP).
+int check_sha(const void *in, uint64_t len, const void *digest);
+
+// Orders n records longest first, stages them on the (device, stream)
+// context and launches the hash kernel (kMaxShaBatch per launch).
+int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t n, int num_cus);
+
 }  // namespace aesctr

@@ -172,3 +172,70 @@ def test_completion_fd_becomes_readable():
         assert fd in r
         os.read(fd, 8)
         assert eng.poll(t) or (eng.wait(t) is None)
+
+
+def test_mixed_cipher_and_hash_requests():
+    """Cipher and SHA-256 requests through one engine: every ciphertext
+    equals the oracle's AES-CTR and every digest the SHA-256 oracle's, with
+    launches that carry both kinds.  Hash requests include the empty
+    message, unaligned inputs and a digest at an odd address."""
+    from oracle import sha
+    torch = torch_cuda()
+    A = lib()
+    g = np.random.default_rng(77)
+    n = 400
+    kinds = g.integers(0, 2, size=n)                  # 0 cipher, 1 hash
+    lens = [int(x) for x in g.integers(0, 200_000, size=n)]
+    lens[3], lens[5] = 0, 1
+    total = sum(lens) + 16 * n
+    src_h = np.frombuffer(g.bytes(total), dtype=np.uint8).copy()
+    src = torch.from_numpy(src_h).cuda()
+    dst = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    dig = torch.zeros(33 * n + 1, dtype=torch.uint8, device="cuda")
+    reqs, meta, pos = [], [], 0
+    for i in range(n):
+        pos += int(g.integers(0, 16))                  # unaligned starts
+        L = lens[i]
+        if kinds[i] == 0 and L > 0:
+            key, nonce, ctr0 = g.bytes(16), g.bytes(12), int(g.integers(0, 1 << 32))
+            reqs.append(A.Request(A.aes_expand_key(key), nonce, ctr0, src.data_ptr() + pos, dst.data_ptr() + pos, L))
+            meta.append(("aes", pos, L, key, nonce, ctr0))
+        else:
+            reqs.append(A.HashRequest(src.data_ptr() + pos, dig.data_ptr() + 33 * i + 1, L))
+            meta.append(("sha", pos, L, i))
+        pos += L
+    log("engine mixed cipher + hash")
+    with A.Engine(budget_bytes=64 * MiB) as eng:
+        tickets = [eng.submit(r) for r in reqs]
+        for t in tickets:
+            eng.wait(t)
+        assert eng.stats()["batches"] >= 1
+    out = dst.cpu().numpy()
+    dg = dig.cpu().numpy()
+    for m in meta:
+        if m[0] == "aes":
+            _, p, L, key, nonce, ctr0 = m
+            assert np.array_equal(out[p:p + L], oracle.ctr(key, nonce, ctr0, src_h[p:p + L])), p
+        else:
+            _, p, L, i = m
+            assert dg[33 * i + 1:33 * i + 33].tobytes() == sha.sha256(src_h[p:p + L].tobytes()), i
+
+
+def test_hash_request_validation():
+    torch = torch_cuda()
+    A = lib()
+    from paper_2607_02630_amd import _native as N
+    import ctypes
+    buf = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    with A.Engine(budget_bytes=16 * MiB) as eng:
+        t = ctypes.c_uint64()
+        d = A.HashRequest(buf, buf.data_ptr() + 16, 64).desc()      # digest inside the message
+        assert A.lib.aes_submit(eng._h, ctypes.byref(d), ctypes.byref(t)) == N.AES_EOVERLAP
+        d = A.HashRequest(buf, None, 64).desc()
+        assert A.lib.aes_submit(eng._h, ctypes.byref(d), ctypes.byref(t)) == N.AES_EINVAL
+        d = A.HashRequest(buf, buf.data_ptr() + 2048, 64).desc()
+        d.reserved = 1
+        assert A.lib.aes_submit(eng._h, ctypes.byref(d), ctypes.byref(t)) == N.AES_EINVAL
+        d.flags = 2                                                    # unknown flag
+        d.reserved = 0
+        assert A.lib.aes_submit(eng._h, ctypes.byref(d), ctypes.byref(t)) == N.AES_EINVAL
