@@ -45,6 +45,7 @@ struct aes_engine {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
     std::vector<std::vector<Req>> inflight;
+    std::vector<int> inflight_status;   // status the in-flight batch completes with
     std::vector<int64_t> launched_ns;
     std::thread driver;
     int efd = -1;
@@ -63,9 +64,15 @@ void notify_fd(int fd)
     }
 }
 
+// Launches one batch on stream s and records the stream's completion event.
+// Returns the batch's status.  *launched tells whether any work reached the
+// stream: if so the caller must keep the batch in flight until the event
+// fires, even when the status is an error, so no buffer is released while a
+// kernel may still touch it.
 int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vector<BatchDesc> &recs,
-                 std::vector<aesctr::ShaRecord> &hashes)
+                 std::vector<aesctr::ShaRecord> &hashes, bool *launched)
 {
+    *launched = false;
     // Cipher records go to the batch kernel, hash records (nr == 0) to the
     // hash kernel; both run on this stream before its completion event.
     recs.clear();
@@ -98,16 +105,24 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
                                     static_cast<int>(grid), 2, false);
         if (rc != AES_OK)
             return rc;
+        *launched = true;
     }
-    if (!hashes.empty() &&
-        (rc = aesctr::launch_sha_records(e->device, e->streams[s], hashes.data(), hashes.size(), e->num_cus)) !=
-            AES_OK)
-        return rc;
+    if (!hashes.empty()) {
+        const int hrc =
+            aesctr::launch_sha_records(e->device, e->streams[s], hashes.data(), hashes.size(), e->num_cus);
+        if (hrc != AES_OK && !*launched)
+            return hrc;
+        rc = hrc;
+        *launched = true;
+    }
     if (hipEventRecord(e->events[s], e->streams[s]) != hipSuccess) {
         note_device_error(hipGetLastError());
+        // No event to poll: wait for whatever reached the stream here.
+        (void)hipStreamSynchronize(e->streams[s]);
+        *launched = false;
         return AES_EDEVICE;
     }
-    return AES_OK;
+    return rc;
 }
 
 void drive(aes_engine *e)
@@ -132,7 +147,7 @@ void drive(aes_engine *e)
             hipError_t q = hipEventQuery(e->events[s]);
             if (q == hipErrorNotReady)
                 continue;
-            const int status = q == hipSuccess ? AES_OK : AES_EDEVICE;
+            const int status = q == hipSuccess ? e->inflight_status[s] : AES_EDEVICE;
             if (q != hipSuccess)
                 note_device_error(hipGetLastError());
             const int64_t now = Core::now_ns();
@@ -147,11 +162,13 @@ void drive(aes_engine *e)
                 continue;
             if (!e->core.take_batch(batch))
                 break;
-            int rc = launch_batch(e, s, batch, recs, hashes);
-            if (rc != AES_OK) {
+            bool launched = false;
+            const int rc = launch_batch(e, s, batch, recs, hashes, &launched);
+            if (!launched) {
                 e->core.complete(batch, rc, Core::now_ns());
                 continue;
             }
+            e->inflight_status[s] = rc;
             if (active++ == 0)
                 busy_since = Core::now_ns();
             e->inflight[s].swap(batch);
@@ -219,6 +236,7 @@ extern "C" int aes_engine_create(const aes_engine_cfg_t *cfg, aes_engine_t **out
     e->num_cus = di.num_cus;
     e->host_buffers = c.host_buffers;
     e->inflight.resize(nstreams);
+    e->inflight_status.assign(nstreams, AES_OK);
     for (int s = 0; s < nstreams; ++s) {
         hipStream_t st;
         hipEvent_t ev;

@@ -91,42 +91,17 @@ int check_sha(const void *in, uint64_t len, const void *digest)
     return AES_OK;
 }
 
-int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t n, int num_cus)
+namespace {
+
+// Stages n records, produced by fill(dst, first, m) for records
+// [first, first + m) in launch order, and launches them (kMaxShaBatch each).
+template <class Fill>
+int stage_and_launch(int device, hipStream_t st, size_t n, int num_cus, Fill fill)
 {
-    if (n == 0)
-        return AES_OK;
     int rc;
     ShaCtx *c = get_ctx(device, st, &rc);
     if (!c)
         return rc;
-
-    // Longest first, so lanes of a wave (consecutive records) hash similar
-    // lengths: a stable counting sort on the bit length of len (O(n); equal
-    // lengths keep the caller's order and skip the pass).
-    thread_local std::vector<uint32_t> order;
-    order.resize(n);
-    uint64_t lo = recs[0].len, hi = recs[0].len;
-    for (size_t i = 1; i < n; ++i) {
-        lo = std::min<uint64_t>(lo, recs[i].len);
-        hi = std::max<uint64_t>(hi, recs[i].len);
-    }
-    if (lo == hi) {
-        std::iota(order.begin(), order.end(), 0u);
-    } else {
-        auto bucket = [](uint64_t len) { return 64 - __builtin_clzll(len | 1); };   // 1..62
-        size_t start[66] = {};
-        for (size_t i = 0; i < n; ++i)
-            ++start[65 - bucket(recs[i].len)];
-        size_t acc = 0;
-        for (size_t &v : start) {
-            const size_t cnt = v;
-            v = acc;
-            acc += cnt;
-        }
-        for (size_t i = 0; i < n; ++i)
-            order[start[65 - bucket(recs[i].len)]++] = static_cast<uint32_t>(i);
-    }
-
     std::lock_guard<std::mutex> lk(c->mu);
     for (size_t first = 0; first < n; first += kMaxShaBatch) {
         const uint32_t m = static_cast<uint32_t>(std::min<size_t>(n - first, kMaxShaBatch));
@@ -134,10 +109,9 @@ int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t
         c->next = (c->next + 1) % kShaSlots;
         if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess)
             return device_error();
-        ShaRecord *s = c->staging[slot];
-        for (uint32_t i = 0; i < m; ++i)
-            s[i] = recs[order[first + i]];
-        if (hipMemcpyAsync(c->dev, s, sizeof(ShaRecord) * m, hipMemcpyHostToDevice, st) != hipSuccess)
+        fill(c->staging[slot], first, m);
+        if (hipMemcpyAsync(c->dev, c->staging[slot], sizeof(ShaRecord) * m, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
             return device_error();
         // One lane per message; at most 16 workgroups of 256 lanes per CU,
         // extra messages looping in grid strides.
@@ -152,6 +126,40 @@ int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t
     return AES_OK;
 }
 
+// Launch order: longest first, so lanes of a wave (consecutive records) hash
+// similar lengths -- a stable counting sort on the bit length (O(n)).
+template <class LenOf>
+void length_order(size_t n, LenOf len_of, std::vector<uint32_t> &order)
+{
+    auto bucket = [](uint64_t len) { return 64 - __builtin_clzll(len | 1); };   // 1..62
+    size_t start[66] = {};
+    for (size_t i = 0; i < n; ++i)
+        ++start[65 - bucket(len_of(i))];
+    size_t acc = 0;
+    for (size_t &v : start) {
+        const size_t cnt = v;
+        v = acc;
+        acc += cnt;
+    }
+    order.resize(n);
+    for (size_t i = 0; i < n; ++i)
+        order[start[65 - bucket(len_of(i))]++] = static_cast<uint32_t>(i);
+}
+
+}  // namespace
+
+int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t n, int num_cus)
+{
+    if (n == 0)
+        return AES_OK;
+    thread_local std::vector<uint32_t> order;
+    length_order(n, [&](size_t i) { return recs[i].len; }, order);
+    return stage_and_launch(device, st, n, num_cus, [&](ShaRecord *dst, size_t first, uint32_t m) {
+        for (uint32_t i = 0; i < m; ++i)
+            dst[i] = recs[order[first + i]];
+    });
+}
+
 }  // namespace aesctr
 
 using namespace aesctr;
@@ -162,21 +170,34 @@ extern "C" int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream)
         return AES_OK;
     if (!desc)
         return AES_EINVAL;
+    uint64_t lo = desc[0].len, hi = desc[0].len;
     for (size_t i = 0; i < n; ++i) {
         if (desc[i].reserved != 0)
             return AES_EINVAL;
         const int rc = check_sha(desc[i].in, desc[i].len, desc[i].digest);
         if (rc != AES_OK)
             return rc;
+        lo = std::min<uint64_t>(lo, desc[i].len);
+        hi = std::max<uint64_t>(hi, desc[i].len);
     }
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc != AES_OK)
         return rc;
-    thread_local std::vector<ShaRecord> recs;
-    recs.resize(n);
-    for (size_t i = 0; i < n; ++i)
-        recs[i] = ShaRecord{reinterpret_cast<uint64_t>(desc[i].in), desc[i].len,
-                            reinterpret_cast<uint64_t>(desc[i].digest), 0};
-    return launch_sha_records(di.ordinal, static_cast<hipStream_t>(stream), recs.data(), n, di.num_cus);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto rec = [&](size_t i) {
+        return ShaRecord{reinterpret_cast<uint64_t>(desc[i].in), desc[i].len,
+                         reinterpret_cast<uint64_t>(desc[i].digest), 0};
+    };
+    if (lo == hi)   // equal lengths: the caller's order, written straight into staging
+        return stage_and_launch(di.ordinal, st, n, di.num_cus, [&](ShaRecord *dst, size_t first, uint32_t m) {
+            for (uint32_t i = 0; i < m; ++i)
+                dst[i] = rec(first + i);
+        });
+    thread_local std::vector<uint32_t> order;
+    length_order(n, [&](size_t i) { return desc[i].len; }, order);
+    return stage_and_launch(di.ordinal, st, n, di.num_cus, [&](ShaRecord *dst, size_t first, uint32_t m) {
+        for (uint32_t i = 0; i < m; ++i)
+            dst[i] = rec(order[first + i]);
+    });
 }

@@ -17,7 +17,7 @@ struct ShaRecord {
     uint64_t pad;
 };
 
-constexpr uint32_t kMaxShaBatch = 1u << 18;   // records per launch (8 MiB table)
+constexpr uint32_t kMaxShaBatch = 1u << 17;   // records per launch (4 MiB table)
 
 int launch_sha256_batch(const ShaRecord *dev_recs, uint32_t n, int grid, hipStream_t st);
 

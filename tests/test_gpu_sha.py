@@ -76,8 +76,8 @@ def test_unaligned_inputs_and_digests(in_align, dig_align):
 
 
 def test_more_messages_than_one_launch():
-    """267,144 messages exceed one launch's table (262,144): the call splits
-    into two launches, each with its own length order."""
+    """267,144 messages exceed one launch's table (131,072): the call splits
+    into three launches."""
     g = np.random.default_rng(3)
     n = (1 << 18) + 5000
     lens = g.integers(0, 200, size=n)
