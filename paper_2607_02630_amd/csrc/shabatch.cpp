@@ -1,13 +1,13 @@
 // shabatch.cpp -- sha256_batch: validation, ordering and staging of the
 // message table, and the launch.
 //
-// Per (device, stream) the library keeps a device table of kMaxShaBatch
-// records and a ring of pinned staging slots; a call orders its messages
-// longest first (lanes of a wave then run for similar lengths), writes them
-// to a free slot, copies the slot to the table and launches the kernel.  A
-// slot is reused only after the event behind its last launch fired; launches
-// on one stream are ordered, so the single device table is never
-// overwritten while a kernel reads it.
+// Per (device, stream) the library keeps a ring of pinned staging slots of
+// kMaxShaBatch records; a call orders its messages longest first (lanes of a
+// wave then run for similar lengths), writes them to a free slot and launches
+// the kernel on it: each lane reads its 32-byte record from the slot over
+// PCIe (zero-copy), so there is no upload to order behind the previous launch
+// and the host fills the next slot while the GPU hashes.  A slot is reused
+// only after the event behind the launch that reads it fired.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -25,8 +25,8 @@ constexpr int kShaSlots = 2;
 
 struct ShaCtx {
     std::mutex mu;
-    ShaRecord *dev = nullptr;
     ShaRecord *staging[kShaSlots] = {};
+    const ShaRecord *dev_view[kShaSlots] = {};   // the slots' device addresses
     hipEvent_t done[kShaSlots] = {};
     bool used[kShaSlots] = {};
     int next = 0;
@@ -46,17 +46,21 @@ ShaCtx *get_ctx(int device, void *stream, int *rc)
     }
     ShaCtx *c = new ShaCtx();
     const size_t bytes = sizeof(ShaRecord) * kMaxShaBatch;
-    if (hipMalloc(reinterpret_cast<void **>(&c->dev), bytes) != hipSuccess) {
-        note_device_error(hipGetLastError());
-        *rc = AES_ENOMEM;
-        return nullptr;   // partially initialised context is leaked deliberately
-    }
     for (int i = 0; i < kShaSlots; ++i) {
-        if (hipHostMalloc(reinterpret_cast<void **>(&c->staging[i]), bytes, hipHostMallocDefault) != hipSuccess) {
+        // Coherent (fine-grained): the kernel reads the slot in place, and a
+        // reused slot must never be served from a line cached by an earlier
+        // launch.
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->staging[i]), bytes, hipHostMallocCoherent) != hipSuccess) {
             note_device_error(hipGetLastError());
             *rc = AES_ENOMEM;
+            return nullptr;   // partially initialised context is leaked deliberately
+        }
+        void *view = nullptr;
+        if (hipHostGetDevicePointer(&view, c->staging[i], 0) != hipSuccess || !view) {
+            *rc = device_error();
             return nullptr;
         }
+        c->dev_view[i] = static_cast<const ShaRecord *>(view);
         if (hipEventCreateWithFlags(&c->done[i], hipEventDisableTiming) != hipSuccess) {
             *rc = device_error();
             return nullptr;
@@ -110,14 +114,11 @@ int stage_and_launch(int device, hipStream_t st, size_t n, int num_cus, Fill fil
         if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess)
             return device_error();
         fill(c->staging[slot], first, m);
-        if (hipMemcpyAsync(c->dev, c->staging[slot], sizeof(ShaRecord) * m, hipMemcpyHostToDevice, st) !=
-            hipSuccess)
-            return device_error();
         // One lane per message; at most 16 workgroups of 256 lanes per CU,
         // extra messages looping in grid strides.
         const uint32_t groups = (m + 255) / 256;
         const int grid = static_cast<int>(std::min<uint32_t>(groups, static_cast<uint32_t>(16 * num_cus)));
-        if ((rc = launch_sha256_batch(c->dev, m, grid, st)) != AES_OK)
+        if ((rc = launch_sha256_batch(c->dev_view[slot], m, grid, st)) != AES_OK)
             return rc;
         if (hipEventRecord(c->done[slot], st) != hipSuccess)
             return device_error();
