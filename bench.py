@@ -267,8 +267,8 @@ def cpu_baseline(W, size, bits, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(the path shards by request on the host, see DESIGN.md)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 (the path shards by request "
+                          "on the host; a multi-GPU run is not implemented)"}))
         sys.exit(2)
     import torch
     import workloads as W
@@ -323,7 +323,7 @@ def main():
     # block; with counter-mode caching of rounds 1-2 this kernel does 27
     # fewer (133 for AES-128, 197 for AES-256), and the peak is taken at the
     # kernel's own count.  Bitsliced kernel: bound by VALU issue (64 lane-ops
-    # per clock per CU, about 814 per AES-128 block).  Derivation in the design doc.
+    # per clock per CU, about 814 per AES-128 block).
     clk = 2.4e9
     if args.variant == 2:
         valu_per_block = 814 if nr == 10 else 814 * 14 // 10

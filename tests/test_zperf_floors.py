@@ -1,7 +1,7 @@
 """Performance floors on the GPU, so a regression fails loudly.
 
 Floors sit well below the measured MI355X figures (recorded beside each) so
-that box-to-box variation does not fail them, while a broken fast path
+that machine-to-machine variation does not fail them, while a broken fast path
 (a fallback, a serialised launch, a shape that leaves CUs idle) does.
 """
 from __future__ import annotations
