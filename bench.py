@@ -143,6 +143,60 @@ def end_to_end_gbs(torch, A, sched, nonce, payload, reps=5):
             h_out.copy_(d_out, non_blocking=True)
         vals.append(n / (t.ms * 1e-3) / 1e9)
     vals = sorted(vals[2:])
+    return vals[len(vals) // 2], h_out
+
+
+def end_to_end_pipelined_gbs(torch, A, sched, nonce, payload, expect, chunk=1 * MiB, n_streams=2, reps=5):
+    """Pinned host buffers, cut into chunks that go H2D -> kernel -> D2H on
+    alternating streams, so one chunk's upload overlaps another's download
+    (PCIe is full duplex).  Chunk i starts at counter 1 + i * chunk / 16."""
+    n = len(payload)
+    h_in = torch.from_numpy(payload).pin_memory()
+    h_out = torch.empty(n, dtype=torch.uint8).pin_memory()
+    d_in = torch.empty(n, dtype=torch.uint8, device="cuda")
+    d_out = torch.empty_like(d_in)
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    cur = torch.cuda.current_stream()
+    vals = []
+    for _ in range(reps + 2):
+        h_out.zero_()
+        with Timer(torch) as t:
+            for s in streams:
+                s.wait_stream(cur)
+            for i, off in enumerate(range(0, n, chunk)):
+                m = min(chunk, n - off)
+                s = streams[i % n_streams]
+                with torch.cuda.stream(s):
+                    d_in[off:off + m].copy_(h_in[off:off + m], non_blocking=True)
+                    A.aes_ctr_crypt(sched, nonce, 1 + off // 16, d_in[off:off + m], d_out[off:off + m], stream=s)
+                    h_out[off:off + m].copy_(d_out[off:off + m], non_blocking=True)
+            for s in streams:
+                cur.wait_stream(s)
+        vals.append(n / (t.ms * 1e-3) / 1e9)
+        if not torch.equal(h_out, expect):
+            raise SystemExit("pipelined end-to-end output differs from the one-stream output")
+    vals = sorted(vals[2:])
+    return vals[len(vals) // 2]
+
+
+def end_to_end_zero_copy_gbs(torch, A, sched, nonce, payload, expect, reps=5):
+    """Pinned host buffers that the kernel reads and writes directly over
+    PCIe: one request through the engine's host_buffers mode, timed on the
+    host from submit to completion."""
+    n = len(payload)
+    h_in = torch.from_numpy(payload).pin_memory()
+    h_out = torch.empty(n, dtype=torch.uint8).pin_memory()
+    vals = []
+    with A.Engine(n_streams=1, host_buffers=True) as eng:
+        req = A.Request(sched, nonce, 1, h_in.data_ptr(), h_out.data_ptr(), n)
+        for _ in range(reps + 2):
+            h_out.zero_()
+            t0 = time.perf_counter()
+            eng.wait(eng.submit(req))
+            vals.append(n / (time.perf_counter() - t0) / 1e9)
+            if not torch.equal(h_out, expect):
+                raise SystemExit("zero-copy end-to-end output differs from the one-stream output")
+    vals = sorted(vals[2:])
     return vals[len(vals) // 2]
 
 
@@ -304,8 +358,14 @@ def main():
     te = eager(torch, A, sched, nonce, ins, outs, min(args.steps, 2000), cfg)
     eager_gbs = args.size * min(args.steps, 2000) / (te.ms * 1e-3) / 1e9
     lat = single_latency_us(torch, A, sched, nonce, ins[0], outs[0], cfg=cfg)
-    e2e = end_to_end_gbs(torch, A, sched, nonce, payload)
-    log(f"eager {eager_gbs:.1f} GB/s, single launch {lat:.1f} us, end-to-end {e2e:.2f} GB/s")
+    e2e, e2e_out = end_to_end_gbs(torch, A, sched, nonce, payload)
+    pipe = {f"{c // 1024} KiB": round(end_to_end_pipelined_gbs(torch, A, sched, nonce, payload, e2e_out, chunk=c), 3)
+            for c in (512 * 1024, 1 * MiB, 2 * MiB) if c < len(payload)}
+    e2e_pipe = max(pipe.values()) if pipe else e2e
+    e2e_zc = end_to_end_zero_copy_gbs(torch, A, sched, nonce, payload, e2e_out)
+    del e2e_out
+    log(f"eager {eager_gbs:.1f} GB/s, single launch {lat:.1f} us, end-to-end {e2e:.2f} GB/s "
+        f"(pipelined copies {e2e_pipe:.2f}, zero-copy {e2e_zc:.2f})")
 
     # Warm: the same buffer pair every launch (in + out stay in the 256 MB
     # Infinity Cache); reported beside the cold figure, never as `value`.
@@ -365,6 +425,9 @@ def main():
         "warm_gbs": round(warm_gbs, 3),
         "single_launch_latency_us": round(lat, 2),
         "end_to_end_pinned_gbs": round(e2e, 3),
+        "end_to_end_pinned_pipelined_gbs": round(e2e_pipe, 3),
+        "end_to_end_pipelined_by_chunk": pipe,
+        "end_to_end_pinned_zero_copy_gbs": round(e2e_zc, 3),
         "device": {"name": props.name, "cus": cus},
     }
     # Calibration for HBM-traffic counters: a plain copy of the same size
@@ -405,7 +468,7 @@ def run_sweep(torch, A, W, args):
                 row = {"kernel_gbs": round(size / (ms * 1e-3) / 1e9, 3), "us_per_launch": round(ms * 1e3, 3),
                        "single_launch_us": round(lat, 2)}
                 if variant == 1:
-                    row["end_to_end_pinned_gbs"] = round(end_to_end_gbs(torch, A, sched, nonce, payload), 3)
+                    row["end_to_end_pinned_gbs"] = round(end_to_end_gbs(torch, A, sched, nonce, payload)[0], 3)
                 out[f"aes{bits}/{'tt' if variant == 1 else 'bs'}/{size}"] = row
                 log(f"sweep {bits} {'tt' if variant == 1 else 'bs'} {size}: {row}")
                 del ins, outs

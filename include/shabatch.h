@@ -39,8 +39,12 @@ typedef struct {
 
 /* Hash n messages (n == 0 is a no-op).  The descriptor array is copied at
  * call time: the caller may reuse it when the call returns.  Asynchronous on
- * `stream`; the descriptors travel through pinned staging buffers that the
- * library keeps per (device, stream).  A message may be at most 2^61 - 1
+ * `stream`; the descriptors travel through staging that the library keeps
+ * per (device, stream) until the process ends: two pinned host buffers and
+ * two device buffers of 4 MiB each, and a side stream for their uploads.
+ * Calls with more than 131,072 messages are cut into launches of that many;
+ * the call returns once the last launch is queued, which may wait for the
+ * launch two before it.  A message may be at most 2^61 - 1
  * bytes (the bit length must fit the 64-bit length field).
  * Errors: AES_EINVAL (null desc with n > 0, null digest, null in with
  * len > 0, reserved != 0), AES_ERANGE (message too long), AES_EOVERLAP

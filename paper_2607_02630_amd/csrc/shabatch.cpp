@@ -1,13 +1,17 @@
 // shabatch.cpp -- sha256_batch: validation, ordering and staging of the
 // message table, and the launch.
 //
-// Per (device, stream) the library keeps a ring of pinned staging slots of
-// kMaxShaBatch records; a call orders its messages longest first (lanes of a
-// wave then run for similar lengths), writes them to a free slot and launches
-// the kernel on it: each lane reads its 32-byte record from the slot over
-// PCIe (zero-copy), so there is no upload to order behind the previous launch
-// and the host fills the next slot while the GPU hashes.  A slot is reused
-// only after the event behind the launch that reads it fired.
+// Per (device, stream) the library keeps two staging slots of kMaxShaBatch
+// records, each a pinned host buffer with a device copy.  A call orders its
+// messages longest first (lanes of a wave then run for similar lengths) and
+// cuts them into launches of up to kMaxShaBatch records:
+//  * the first launch of a call reads its records from the pinned slot in
+//    place, over PCIe (zero-copy), so nothing is uploaded ahead of it;
+//  * every later launch's records are uploaded to the slot's device copy on
+//    a side stream while the previous launch hashes, and the launch waits
+//    for that upload only.
+// A slot is refilled only after the event behind the launch that read it
+// fired, and the host fills the next slot while the GPU hashes.
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -26,8 +30,11 @@ constexpr int kShaSlots = 2;
 struct ShaCtx {
     std::mutex mu;
     ShaRecord *staging[kShaSlots] = {};
-    const ShaRecord *dev_view[kShaSlots] = {};   // the slots' device addresses
-    hipEvent_t done[kShaSlots] = {};
+    const ShaRecord *host_view[kShaSlots] = {};  // the pinned slots' device addresses
+    ShaRecord *dev_copy[kShaSlots] = {};         // device-memory copies of the slots
+    hipEvent_t done[kShaSlots] = {};             // the launch that read the slot
+    hipEvent_t uploaded[kShaSlots] = {};         // the slot's upload to dev_copy
+    hipStream_t upload = nullptr;                // side stream of the uploads
     bool used[kShaSlots] = {};
     int next = 0;
 };
@@ -46,22 +53,29 @@ ShaCtx *get_ctx(int device, void *stream, int *rc)
     }
     ShaCtx *c = new ShaCtx();
     const size_t bytes = sizeof(ShaRecord) * kMaxShaBatch;
+    // A partially initialised context is leaked deliberately on error.
+    if (hipStreamCreateWithFlags(&c->upload, hipStreamNonBlocking) != hipSuccess) {
+        *rc = device_error();
+        return nullptr;
+    }
     for (int i = 0; i < kShaSlots; ++i) {
         // Coherent (fine-grained): the kernel reads the slot in place, and a
         // reused slot must never be served from a line cached by an earlier
         // launch.
-        if (hipHostMalloc(reinterpret_cast<void **>(&c->staging[i]), bytes, hipHostMallocCoherent) != hipSuccess) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->staging[i]), bytes, hipHostMallocCoherent) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&c->dev_copy[i]), bytes) != hipSuccess) {
             note_device_error(hipGetLastError());
             *rc = AES_ENOMEM;
-            return nullptr;   // partially initialised context is leaked deliberately
+            return nullptr;
         }
         void *view = nullptr;
         if (hipHostGetDevicePointer(&view, c->staging[i], 0) != hipSuccess || !view) {
             *rc = device_error();
             return nullptr;
         }
-        c->dev_view[i] = static_cast<const ShaRecord *>(view);
-        if (hipEventCreateWithFlags(&c->done[i], hipEventDisableTiming) != hipSuccess) {
+        c->host_view[i] = static_cast<const ShaRecord *>(view);
+        if (hipEventCreateWithFlags(&c->done[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->uploaded[i], hipEventDisableTiming) != hipSuccess) {
             *rc = device_error();
             return nullptr;
         }
@@ -118,7 +132,19 @@ int stage_and_launch(int device, hipStream_t st, size_t n, int num_cus, Fill fil
         // extra messages looping in grid strides.
         const uint32_t groups = (m + 255) / 256;
         const int grid = static_cast<int>(std::min<uint32_t>(groups, static_cast<uint32_t>(16 * num_cus)));
-        if ((rc = launch_sha256_batch(c->dev_view[slot], m, grid, st)) != AES_OK)
+        const ShaRecord *recs = c->host_view[slot];
+        if (first > 0) {
+            // The upload may start at once: it waits for nothing on `st`
+            // (the slot's previous reader finished, see above), so it runs
+            // beside the launch before it.
+            recs = c->dev_copy[slot];
+            if (hipMemcpyAsync(c->dev_copy[slot], c->staging[slot], sizeof(ShaRecord) * m, hipMemcpyHostToDevice,
+                               c->upload) != hipSuccess ||
+                hipEventRecord(c->uploaded[slot], c->upload) != hipSuccess ||
+                hipStreamWaitEvent(st, c->uploaded[slot], 0) != hipSuccess)
+                return device_error();
+        }
+        if ((rc = launch_sha256_batch(recs, m, grid, st)) != AES_OK)
             return rc;
         if (hipEventRecord(c->done[slot], st) != hipSuccess)
             return device_error();
