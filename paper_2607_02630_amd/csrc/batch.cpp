@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "aesctr_internal.h"
+#include "host_pool.h"
 #include "tune.h"
 
 namespace aesctr {
@@ -27,6 +28,9 @@ namespace {
 
 constexpr int kSlots = 4;
 constexpr size_t kTableBytes = sizeof(BatchHeader) + sizeof(BatchDesc) * kMaxBatch;
+
+// Descriptors per part of the host's parallel validation.
+constexpr size_t kCheckGrain = 4096;
 
 struct BatchShape {
     int tile_bytes, wg, grid, bpl, use_graph;
@@ -136,17 +140,17 @@ int build_graph(BatchCtx *c, int s, int grid, int bpl)
     return AES_OK;
 }
 
-// Copy n prebuilt records into staging slot `buf`, assigning first tiles.
-// Returns the bytes to upload, or 0 if the tile count would overflow.
-size_t stage(uint8_t *buf, const BatchDesc *recs, size_t n, uint32_t tile_blocks)
+// Completes staging slot `buf` whose n records are written: assigns first
+// tiles and fills the header.  Returns the bytes to upload, or 0 if the tile
+// count would overflow.
+size_t finish_stage(uint8_t *buf, size_t n, uint32_t tile_blocks)
 {
     BatchHeader *h = reinterpret_cast<BatchHeader *>(buf);
     BatchDesc *out = reinterpret_cast<BatchDesc *>(buf + sizeof(BatchHeader));
     uint64_t tiles = 0;
     for (size_t i = 0; i < n; ++i) {
-        out[i] = recs[i];
         out[i].tile0 = static_cast<uint32_t>(tiles);
-        const uint64_t blocks = (recs[i].len + 15) / 16;
+        const uint64_t blocks = (out[i].len + 15) / 16;
         tiles += (blocks + tile_blocks - 1) / tile_blocks;
         if (tiles > 0x7fffffffu)
             return 0;
@@ -157,6 +161,66 @@ size_t stage(uint8_t *buf, const BatchDesc *recs, size_t n, uint32_t tile_blocks
     h->tile_blocks = tile_blocks;
     h->next = 0;
     return sizeof(BatchHeader) + n * sizeof(BatchDesc);
+}
+
+// Records per part of the host's parallel record building.
+constexpr size_t kRecordGrain = 256;
+
+// Stages n records, produced by fill(dst, first, m) for records
+// [first, first + m), and launches them (kMaxBatch per launch) through the
+// slot's captured graph or a plain copy + launch.
+template <class Fill>
+int launch_filled(int device, hipStream_t st, size_t n, int tile_bytes, int grid, int bpl, bool use_graph,
+                  Fill fill)
+{
+    int rc;
+    BatchCtx *c = get_ctx(device, st, &rc);
+    if (!c)
+        return rc;
+    const uint32_t tile_blocks = static_cast<uint32_t>(tile_bytes / 16);
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (size_t first = 0; first < n; first += kMaxBatch) {
+        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
+        const int slot = c->next_slot;
+        c->next_slot = (c->next_slot + 1) % kSlots;
+        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
+            note_device_error(hipGetLastError());
+            return AES_EDEVICE;
+        }
+        BatchDesc *out = reinterpret_cast<BatchDesc *>(c->staging[slot] + sizeof(BatchHeader));
+        HostPool::get().parallel_for(m, kRecordGrain, [&](size_t, size_t b, size_t e) {
+            fill(out + b, first + b, e - b);
+        });
+        const size_t bytes = finish_stage(c->staging[slot], m, tile_blocks);
+        if (bytes == 0)
+            return AES_ERANGE;
+        if (use_graph) {
+            SlotGraph &sg = c->g[slot];
+            if (!sg.exec || sg.grid != grid || sg.bpl != bpl) {
+                if ((rc = build_graph(c, slot, grid, bpl)) != AES_OK)
+                    return rc;
+            }
+            if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
+                                                  hipMemcpyHostToDevice) != hipSuccess ||
+                hipGraphLaunch(sg.exec, st) != hipSuccess) {
+                note_device_error(hipGetLastError());
+                return AES_EDEVICE;
+            }
+        } else {
+            if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+                note_device_error(hipGetLastError());
+                return AES_EDEVICE;
+            }
+            if ((rc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, st)) != AES_OK)
+                return rc;
+        }
+        if (hipEventRecord(c->done[slot], st) != hipSuccess) {
+            note_device_error(hipGetLastError());
+            return AES_EDEVICE;
+        }
+        c->used[slot] = true;
+    }
+    return AES_OK;
 }
 
 }  // namespace
@@ -202,50 +266,10 @@ int check_desc(const aes_ctr_desc_t &d)
 int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
                    int bpl, bool use_graph)
 {
-    int rc;
-    BatchCtx *c = get_ctx(device, st, &rc);
-    if (!c)
-        return rc;
-    const uint32_t tile_blocks = static_cast<uint32_t>(tile_bytes / 16);
-    std::lock_guard<std::mutex> lk(c->mu);
-    for (size_t first = 0; first < n; first += kMaxBatch) {
-        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
-        const int slot = c->next_slot;
-        c->next_slot = (c->next_slot + 1) % kSlots;
-        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
-            note_device_error(hipGetLastError());
-            return AES_EDEVICE;
-        }
-        const size_t bytes = stage(c->staging[slot], recs + first, m, tile_blocks);
-        if (bytes == 0)
-            return AES_ERANGE;
-        if (use_graph) {
-            SlotGraph &sg = c->g[slot];
-            if (!sg.exec || sg.grid != grid || sg.bpl != bpl) {
-                if ((rc = build_graph(c, slot, grid, bpl)) != AES_OK)
-                    return rc;
-            }
-            if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
-                                                  hipMemcpyHostToDevice) != hipSuccess ||
-                hipGraphLaunch(sg.exec, st) != hipSuccess) {
-                note_device_error(hipGetLastError());
-                return AES_EDEVICE;
-            }
-        } else {
-            if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
-                note_device_error(hipGetLastError());
-                return AES_EDEVICE;
-            }
-            if ((rc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, st)) != AES_OK)
-                return rc;
-        }
-        if (hipEventRecord(c->done[slot], st) != hipSuccess) {
-            note_device_error(hipGetLastError());
-            return AES_EDEVICE;
-        }
-        c->used[slot] = true;
-    }
-    return AES_OK;
+    return launch_filled(device, st, n, tile_bytes, grid, bpl, use_graph,
+                         [recs](BatchDesc *dst, size_t first, size_t m) {
+                             memcpy(dst, recs + first, m * sizeof(BatchDesc));
+                         });
 }
 
 }  // namespace aesctr
@@ -259,10 +283,27 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
         return AES_OK;
     if (!desc)
         return AES_EINVAL;
-    for (size_t i = 0; i < n; ++i) {
-        int rc = check_desc(desc[i]);
-        if (rc != AES_OK)
-            return rc;
+    // Validation and the payload total, over parts in parallel; the status of
+    // the first failing descriptor wins, as in a serial scan.
+    struct Scan {
+        int rc;
+        uint64_t bytes;
+    };
+    const size_t parts = HostPool::parts(n, kCheckGrain);
+    Scan scan[HostPool::kMaxParts];
+    HostPool::get().parallel_for(n, kCheckGrain, [&](size_t p, size_t b, size_t e) {
+        Scan r{AES_OK, 0};
+        for (size_t i = b; i < e && r.rc == AES_OK; ++i) {
+            r.rc = check_desc(desc[i]);
+            r.bytes += desc[i].len;
+        }
+        scan[p] = r;
+    });
+    uint64_t total_bytes = 0;
+    for (size_t p = 0; p < parts; ++p) {
+        if (scan[p].rc != AES_OK)
+            return scan[p].rc;
+        total_bytes += scan[p].bytes;
     }
     // Tile size 0 = sized to the batch (batch_tile_bytes); two blocks per lane.
     BatchShape sh{0, 1024, 0, 2, 1};
@@ -301,17 +342,14 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
     if (cs != hipStreamCaptureStatusNone)
         return AES_EINVAL;
 
-    if (sh.tile_bytes == 0) {
-        uint64_t bytes = 0;
-        for (size_t i = 0; i < n; ++i)
-            bytes += desc[i].len;
-        sh.tile_bytes = static_cast<int>(batch_tile_bytes(bytes, di.num_cus));
-    }
-    thread_local std::vector<BatchDesc> recs;
-    recs.resize(n);
-    for (size_t i = 0; i < n; ++i)
-        make_batch_record(desc[i], &recs[i]);
-    return launch_records(di.ordinal, st, recs.data(), n, sh.tile_bytes, sh.grid, sh.bpl, sh.use_graph != 0);
+    if (sh.tile_bytes == 0)
+        sh.tile_bytes = static_cast<int>(batch_tile_bytes(total_bytes, di.num_cus));
+    // Records are built straight into the pinned staging slot.
+    return launch_filled(di.ordinal, st, n, sh.tile_bytes, sh.grid, sh.bpl, sh.use_graph != 0,
+                         [desc](BatchDesc *dst, size_t first, size_t m) {
+                             for (size_t i = 0; i < m; ++i)
+                                 make_batch_record(desc[first + i], dst + i);
+                         });
 }
 
 extern "C" int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream)

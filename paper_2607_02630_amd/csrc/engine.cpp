@@ -64,6 +64,16 @@ void notify_fd(int fd)
     }
 }
 
+// Waits for everything queued on stream s, after a launch call failed
+// part-way (a call that launches several chunks may fail after the first):
+// the batch is then completed at once, and no kernel may still touch its
+// buffers.
+int drain_after_error(aes_engine *e, int s, int rc)
+{
+    (void)hipStreamSynchronize(e->streams[s]);
+    return rc;
+}
+
 // Launches one batch on stream s and records the stream's completion event.
 // Returns the batch's status.  *launched tells whether any work reached the
 // stream: if so the caller must keep the batch in flight until the event
@@ -104,14 +114,14 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
         rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), static_cast<int>(tile),
                                     static_cast<int>(grid), 2, false);
         if (rc != AES_OK)
-            return rc;
+            return drain_after_error(e, s, rc);
         *launched = true;
     }
     if (!hashes.empty()) {
         const int hrc =
             aesctr::launch_sha_records(e->device, e->streams[s], hashes.data(), hashes.size(), e->num_cus);
         if (hrc != AES_OK && !*launched)
-            return hrc;
+            return drain_after_error(e, s, hrc);
         rc = hrc;
         *launched = true;
     }

@@ -5,11 +5,12 @@
 // records, each a pinned host buffer with a device copy.  A call orders its
 // messages longest first (lanes of a wave then run for similar lengths) and
 // cuts them into launches of up to kMaxShaBatch records:
-//  * the first launch of a call reads its records from the pinned slot in
-//    place, over PCIe (zero-copy), so nothing is uploaded ahead of it;
-//  * every later launch's records are uploaded to the slot's device copy on
-//    a side stream while the previous launch hashes, and the launch waits
-//    for that upload only.
+//  * a launch queued on an idle stream (the first of a call, when nothing
+//    else is queued) reads its records from the pinned slot in place, over
+//    PCIe (zero-copy), so nothing is uploaded ahead of it;
+//  * every other launch's records are uploaded to the slot's device copy on
+//    a side stream while the work queued before it runs, and the launch
+//    waits for that upload only.
 // A slot is refilled only after the event behind the launch that read it
 // fired, and the host fills the next slot while the GPU hashes.
 #include <algorithm>
@@ -20,12 +21,15 @@
 #include <vector>
 
 #include "../../include/shabatch.h"
+#include "host_pool.h"
 #include "shabatch_internal.h"
 
 namespace aesctr {
 namespace {
 
 constexpr int kShaSlots = 2;
+// Descriptors per part of the host's parallel validation and staging.
+constexpr size_t kShaGrain = 16384;
 
 struct ShaCtx {
     std::mutex mu;
@@ -127,16 +131,19 @@ int stage_and_launch(int device, hipStream_t st, size_t n, int num_cus, Fill fil
         c->next = (c->next + 1) % kShaSlots;
         if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess)
             return device_error();
-        fill(c->staging[slot], first, m);
+        ShaRecord *dst = c->staging[slot];
+        HostPool::get().parallel_for(m, kShaGrain, [&](size_t, size_t b, size_t e) {
+            fill(dst + b, first + b, static_cast<uint32_t>(e - b));
+        });
         // One lane per message; at most 16 workgroups of 256 lanes per CU,
         // extra messages looping in grid strides.
         const uint32_t groups = (m + 255) / 256;
         const int grid = static_cast<int>(std::min<uint32_t>(groups, static_cast<uint32_t>(16 * num_cus)));
         const ShaRecord *recs = c->host_view[slot];
-        if (first > 0) {
+        if (first > 0 || hipStreamQuery(st) != hipSuccess) {
             // The upload may start at once: it waits for nothing on `st`
             // (the slot's previous reader finished, see above), so it runs
-            // beside the launch before it.
+            // beside the work queued before the launch.
             recs = c->dev_copy[slot];
             if (hipMemcpyAsync(c->dev_copy[slot], c->staging[slot], sizeof(ShaRecord) * m, hipMemcpyHostToDevice,
                                c->upload) != hipSuccess ||
@@ -179,7 +186,11 @@ int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t
 {
     if (n == 0)
         return AES_OK;
-    thread_local std::vector<uint32_t> order;
+    // The fill runs on pool threads too: they must see this thread's order
+    // (a lambda does not capture a thread_local, it names the running
+    // thread's own), hence the plain reference.
+    thread_local std::vector<uint32_t> tl_order;
+    std::vector<uint32_t> &order = tl_order;
     length_order(n, [&](size_t i) { return recs[i].len; }, order);
     return stage_and_launch(device, st, n, num_cus, [&](ShaRecord *dst, size_t first, uint32_t m) {
         for (uint32_t i = 0; i < m; ++i)
@@ -197,15 +208,30 @@ extern "C" int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream)
         return AES_OK;
     if (!desc)
         return AES_EINVAL;
-    uint64_t lo = desc[0].len, hi = desc[0].len;
-    for (size_t i = 0; i < n; ++i) {
-        if (desc[i].reserved != 0)
-            return AES_EINVAL;
-        const int rc = check_sha(desc[i].in, desc[i].len, desc[i].digest);
-        if (rc != AES_OK)
-            return rc;
-        lo = std::min<uint64_t>(lo, desc[i].len);
-        hi = std::max<uint64_t>(hi, desc[i].len);
+    // Validation and the length range, over parts in parallel; the status of
+    // the first failing descriptor wins, as in a serial scan.
+    struct Scan {
+        int rc;
+        uint64_t lo, hi;
+    };
+    HostPool &pool = HostPool::get();
+    const size_t parts = HostPool::parts(n, kShaGrain);
+    Scan scan[HostPool::kMaxParts];
+    pool.parallel_for(n, kShaGrain, [&](size_t p, size_t b, size_t e) {
+        Scan r{AES_OK, UINT64_MAX, 0};
+        for (size_t i = b; i < e && r.rc == AES_OK; ++i) {
+            r.rc = desc[i].reserved != 0 ? AES_EINVAL : check_sha(desc[i].in, desc[i].len, desc[i].digest);
+            r.lo = std::min<uint64_t>(r.lo, desc[i].len);
+            r.hi = std::max<uint64_t>(r.hi, desc[i].len);
+        }
+        scan[p] = r;
+    });
+    uint64_t lo = UINT64_MAX, hi = 0;
+    for (size_t p = 0; p < parts; ++p) {
+        if (scan[p].rc != AES_OK)
+            return scan[p].rc;
+        lo = std::min(lo, scan[p].lo);
+        hi = std::max(hi, scan[p].hi);
     }
     DeviceInfo di;
     int rc = device_info(&di);
@@ -221,7 +247,8 @@ extern "C" int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream)
             for (uint32_t i = 0; i < m; ++i)
                 dst[i] = rec(first + i);
         });
-    thread_local std::vector<uint32_t> order;
+    thread_local std::vector<uint32_t> tl_order;
+    std::vector<uint32_t> &order = tl_order;   // see launch_sha_records
     length_order(n, [&](size_t i) { return desc[i].len; }, order);
     return stage_and_launch(di.ordinal, st, n, di.num_cus, [&](ShaRecord *dst, size_t first, uint32_t m) {
         for (uint32_t i = 0; i < m; ++i)

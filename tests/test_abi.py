@@ -172,3 +172,48 @@ def test_sha_validation_before_device():
     arr[0].in_ = 0x1000
     arr[1].in_, arr[1].len, arr[1].digest, arr[1].reserved = 0x2000, 8, 0x3000, 7
     assert L.sha256_batch(arr, 2, None) == N.AES_EINVAL
+
+
+def test_sha_validation_of_a_large_batch_reports_the_first_error():
+    # Large batches are validated in parallel parts (here four, of 17,500
+    # descriptors); the status is still the one of the first failing
+    # descriptor, as a serial scan would return.
+    n = 70_000
+    arr = (N.sha256_desc_t * n)()
+    v = np.frombuffer(arr, dtype=np.uint64).reshape(n, 4)
+    idx = np.arange(n, dtype=np.uint64)
+    v[:, 0] = 0x10_0000_0000 + idx * 4096         # input
+    v[:, 1] = 4096                                # length
+    v[:, 2] = 0x20_0000_0000 + idx * 32           # digest
+    v[:, 3] = 0                                   # reserved
+    v[66_000, 3] = 1                              # EINVAL, last
+    v[50_000, 1] = 1 << 61                        # ERANGE
+    v[30_000, 2] = v[30_000, 0] + 64              # EOVERLAP, first
+    assert A.lib.sha256_batch(arr, n, None) == N.AES_EOVERLAP
+    v[30_000, 2] = 0x20_0000_0000 + 30_000 * 32
+    assert A.lib.sha256_batch(arr, n, None) == N.AES_ERANGE
+    v[50_000, 1] = 4096
+    assert A.lib.sha256_batch(arr, n, None) == N.AES_EINVAL
+
+
+def test_batch_validation_of_a_large_batch_reports_the_first_error():
+    n = 10_000   # two parts of 5,000 descriptors
+    s = A.aes_expand_key(bytes(16))
+    bad = A.aes_expand_key(bytes(16))
+    bad.nr = 12
+    arr = (N.aes_ctr_desc_t * n)()
+    for i in range(n):
+        d = arr[i]
+        d.in_ = 0x10_0000_0000 + i * 8192
+        d.out = 0x20_0000_0000 + i * 8192
+        d.len = 4096
+        d.sched = ctypes.pointer(s)
+    arr[9_000].flags = 3                          # EINVAL, last
+    arr[7_000].len = (1 << 36) + 16               # ERANGE
+    arr[3_000].out = arr[3_000].in_ + 8           # EOVERLAP, first
+    assert A.lib.aes_ctr_crypt_batch(arr, n, None) == N.AES_EOVERLAP
+    arr[3_000].out = 0x20_0000_0000 + 3_000 * 8192
+    assert A.lib.aes_ctr_crypt_batch(arr, n, None) == N.AES_ERANGE
+    arr[7_000].len = 4096
+    arr[8_000].sched = ctypes.pointer(bad)        # EINVAL, before the flags one
+    assert A.lib.aes_ctr_crypt_batch(arr, n, None) == N.AES_EINVAL
