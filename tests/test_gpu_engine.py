@@ -148,6 +148,21 @@ def test_pinned_host_buffers():
     check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(6))
 
 
+def test_pinned_host_buffers_large_requests_alone():
+    # Each request runs as a batch of its own, so a zero-copy launch takes
+    # its larger tiles (several steps per wave); odd lengths leave the later
+    # requests unaligned and with partial final blocks.
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_requests(torch, 8, 9, sizes=(8 * MiB + 5, 3 * MiB + 17, 64 * KiB + 1),
+                                               mix=(0.4, 0.3, 0.3), host=True)
+    log(f"pinned alone: {[L for L in lens]}")
+    with A.Engine(budget_bytes=256 * MiB, host_buffers=True) as eng:
+        for r in reqs:
+            eng.wait(eng.submit(r[4]))
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(10))
+
+
 def test_destroy_drains_submitted_work():
     torch = torch_cuda()
     A = lib()
