@@ -164,7 +164,9 @@ typedef struct {
  * descriptor table (the shape of the paper's job queue, Listing 1, with every
  * job handed to the device at once).  The descriptors, schedules and tile
  * index are staged in pinned host memory and copied by a node of a captured
- * HIP graph, replayed on each call.  Each request's output equals
+ * HIP graph, replayed on each call.  A batch of at most 8 requests skips the
+ * table: its records travel in the kernel's argument block, so no copy
+ * precedes the launch.  Each request's output equals
  * aes_ctr_crypt on that request alone.  n == 0 is a no-op.
  * Errors: AES_EINVAL (null desc with n > 0, null sched, flags != 0, a
  * stream that is being captured -- the call launches its own graph and its
@@ -176,8 +178,9 @@ int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream);
 /* Batch launch shape: tile_bytes (bytes of a request one wave-tile covers,
  * multiple of 1024), wg_size, grid, blocks_per_lane; zero = default (tiles
  * sized to the batch, about sixteen per CU within 2-64 KiB; 2 blocks per
- * lane; 1024-thread workgroups, one per CU; a tune cache may override).  use_graph: 1 = captured graph, 0 = plain copy
- * + launch; a call without cfg uses the graph. */
+ * lane; 1024-thread workgroups, one per CU; a tune cache may override).
+ * use_graph: 1 = captured graph, 0 = plain copy + launch; a call without cfg
+ * uses the graph; batches of at most 8 requests use neither. */
 typedef struct {
     int32_t tile_bytes;
     int32_t wg_size;

@@ -107,6 +107,27 @@ static_assert(sizeof(BatchDesc) == 320, "descriptor layout");
 
 int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream_t st);
 
+// Small batches (at most kSmallBatch requests) travel in the kernel argument
+// block instead of a device table: the same fields as BatchDesc, without its
+// 64-byte alignment (kernel arguments are 16-byte aligned).
+constexpr uint32_t kSmallBatch = 8;
+
+struct SmallRec {
+    uint64_t in, out, len;
+    uint32_t ctr0, x0, nr, aligned;
+    uint32_t k1[4];
+    uint32_t tile0;
+    uint32_t rk[60];
+};
+
+struct SmallBatchArgs {
+    uint32_t n, total_tiles, tile_blocks, pad;
+    SmallRec r[kSmallBatch];
+};
+static_assert(sizeof(SmallBatchArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
+int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int wg, int bpl, hipStream_t st);
+
 // Host side of the batch path (batch.cpp).  make_batch_record expands one
 // validated request into its device record; launch_records stages up to any
 // number of records (kMaxBatch per launch) on the (device, stream) context and

@@ -169,10 +169,44 @@ constexpr size_t kRecordGrain = 256;
 // Stages n records, produced by fill(dst, first, m) for records
 // [first, first + m), and launches them (kMaxBatch per launch) through the
 // slot's captured graph or a plain copy + launch.
+// A batch of at most kSmallBatch requests goes in the kernel's argument block
+// (no staging slot, no upload).  Returns AES_OK, AES_ERANGE or AES_EDEVICE.
+template <class Fill>
+int launch_small(hipStream_t st, size_t n, uint32_t tile_blocks, int grid, int bpl, Fill fill)
+{
+    BatchDesc recs[kSmallBatch];
+    fill(recs, 0, n);
+    SmallBatchArgs args{};
+    uint64_t tiles = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const BatchDesc &d = recs[i];
+        SmallRec &r = args.r[i];
+        r.in = d.in;
+        r.out = d.out;
+        r.len = d.len;
+        r.ctr0 = d.ctr0;
+        r.x0 = d.x0;
+        r.nr = d.nr;
+        r.aligned = d.aligned;
+        memcpy(r.k1, d.k1, sizeof(r.k1));
+        memcpy(r.rk, d.rk, sizeof(r.rk));
+        r.tile0 = static_cast<uint32_t>(tiles);
+        tiles += ((d.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
+        if (tiles > 0x7fffffffu)
+            return AES_ERANGE;
+    }
+    args.n = static_cast<uint32_t>(n);
+    args.total_tiles = static_cast<uint32_t>(tiles);
+    args.tile_blocks = tile_blocks;
+    return launch_ctr_batch_small(args, grid, 1024, bpl, st);
+}
+
 template <class Fill>
 int launch_filled(int device, hipStream_t st, size_t n, int tile_bytes, int grid, int bpl, bool use_graph,
                   Fill fill)
 {
+    if (n <= kSmallBatch)
+        return launch_small(st, n, static_cast<uint32_t>(tile_bytes / 16), grid, bpl, fill);
     int rc;
     BatchCtx *c = get_ctx(device, st, &rc);
     if (!c)

@@ -86,6 +86,43 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const C
     }
 }
 
+// Tile t of request R (a BatchDesc in the device table or a SmallRec in the
+// kernel arguments; both wave-uniform, so their fields arrive by scalar
+// loads): the request's key material and pointers, then the tile's blocks.
+template <int BPL, class Rec>
+__device__ __forceinline__ void request_tile(const TTable<kBatchCopies> &tt, const Rec &R, uint32_t t,
+                                             uint32_t tile_blocks, uint32_t lane)
+{
+    CtrArgs a;
+    a.in = reinterpret_cast<const uint8_t *>(R.in);
+    a.out = reinterpret_cast<uint8_t *>(R.out);
+    a.len = R.len;
+    a.ctr0 = R.ctr0;
+    a.x0 = R.x0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        a.k1[c] = R.k1[c];
+    const uint32_t nr = R.nr;
+    const uint32_t nrk = 4 * (nr + 1);
+#pragma unroll
+    for (int i = 0; i < 60; ++i)
+        a.rk[i] = i < 44 || nrk > 44 ? R.rk[i] : 0;
+    const uint64_t nblocks = (a.len + 15) >> 4;
+    const uint64_t b0 = static_cast<uint64_t>(t - R.tile0) * tile_blocks;
+    const uint64_t b1 = b0 + tile_blocks < nblocks ? b0 + tile_blocks : nblocks;
+    if (R.aligned) {
+        if (nr == 10)
+            run_tile<10, BPL, true>(tt, a, b0, b1, lane);
+        else
+            run_tile<14, BPL, true>(tt, a, b0, b1, lane);
+    } else {
+        if (nr == 10)
+            run_tile<10, BPL, false>(tt, a, b0, b1, lane);
+        else
+            run_tile<14, BPL, false>(tt, a, b0, b1, lane);
+    }
+}
+
 // table: the uploaded header + descriptors, read-only here (so request fields
 // come in through the scalar cache); counter: the header's `next` word, the
 // only thing the kernel writes besides the outputs.
@@ -135,36 +172,38 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
                 hi = mid - 1;
         }
         const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
-        const BatchDesc *R = desc + r;
-        CtrArgs a;
-        a.in = reinterpret_cast<const uint8_t *>(R->in);
-        a.out = reinterpret_cast<uint8_t *>(R->out);
-        a.len = R->len;
-        a.ctr0 = R->ctr0;
-        a.x0 = R->x0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            a.k1[c] = R->k1[c];
-        const uint32_t nr = R->nr;
-        const uint32_t nrk = 4 * (nr + 1);
-#pragma unroll
-        for (int i = 0; i < 60; ++i)
-            a.rk[i] = i < 44 || nrk > 44 ? R->rk[i] : 0;
-        const uint64_t nblocks = (a.len + 15) >> 4;
-        const uint64_t b0 = static_cast<uint64_t>(t - R->tile0) * tile_blocks;
-        const uint64_t b1 = b0 + tile_blocks < nblocks ? b0 + tile_blocks : nblocks;
-        if (R->aligned) {
-            if (nr == 10)
-                run_tile<10, BPL, true>(tt, a, b0, b1, lane);
-            else
-                run_tile<14, BPL, true>(tt, a, b0, b1, lane);
-        } else {
-            if (nr == 10)
-                run_tile<10, BPL, false>(tt, a, b0, b1, lane);
-            else
-                run_tile<14, BPL, false>(tt, a, b0, b1, lane);
-        }
+        request_tile<BPL>(tt, desc[r], t, tile_blocks, lane);
         t = waves + __builtin_amdgcn_readfirstlane(claim);
+    }
+}
+
+// A batch of at most kSmallBatch requests whose records travel in the kernel
+// argument block: no descriptor upload goes ahead of the launch (a separate
+// host-to-device copy adds about 20 us to a small batch's latency).  Tiles
+// are assigned statically, wave w taking tiles w, w + W, w + 2W, ... (W
+// waves, numbered as in ctr_batch_kernel), so no work counter is needed.
+template <int BPL>
+__global__ __launch_bounds__(kBatchWG) void ctr_batch_small_kernel(const SmallBatchArgs args)
+{
+    __shared__ uint32_t lds[kLdsWords];
+
+    uint32_t tv[kFillStores / kBatchWG];
+    fill_read<kBatchWG>(tv);
+    fill_write<kBatchCopies, kBatchWG>(lds, tv);
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & 63;
+    TTable<kBatchCopies> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
+    const uint32_t waves = gridDim.x * (kBatchWG / 64);
+    const uint32_t n = args.n;
+    for (uint32_t t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+         t < args.total_tiles; t += waves) {
+        // Last request whose first tile is <= t (skips empty requests).
+        uint32_t r = 0;
+        for (uint32_t i = 1; i < n; ++i)
+            if (args.r[i].tile0 <= t)
+                r = i;
+        request_tile<BPL>(tt, args.r[r], t, args.tile_blocks, lane);
     }
 }
 
@@ -180,6 +219,19 @@ int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream
     switch (bpl) {
     case 1: hipLaunchKernelGGL(ctr_batch_kernel<1>, dim3(grid), dim3(kBatchWG), 0, st, t, ctr); break;
     case 2: hipLaunchKernelGGL(ctr_batch_kernel<2>, dim3(grid), dim3(kBatchWG), 0, st, t, ctr); break;
+    default: return AES_EINVAL;
+    }
+    return launch_status();
+}
+
+int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int wg, int bpl, hipStream_t st)
+{
+    if (wg != kBatchWG || grid <= 0 || grid > kMaxBatchGrid || args.n > kSmallBatch)
+        return AES_EINVAL;
+    (void)hipGetLastError();   // not ours: left by earlier calls
+    switch (bpl) {
+    case 1: hipLaunchKernelGGL(ctr_batch_small_kernel<1>, dim3(grid), dim3(kBatchWG), 0, st, args); break;
+    case 2: hipLaunchKernelGGL(ctr_batch_small_kernel<2>, dim3(grid), dim3(kBatchWG), 0, st, args); break;
     default: return AES_EINVAL;
     }
     return launch_status();

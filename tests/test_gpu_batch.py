@@ -117,6 +117,30 @@ def test_tiling_shapes(tile_bytes, bpl):
         b.check_full(i)
 
 
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 9])
+@pytest.mark.parametrize("misalign", [False, True])
+def test_small_batches_through_kernel_arguments(n, misalign):
+    # Up to 8 requests travel in the kernel's argument block (no table
+    # upload, static tile assignment); 9 takes the table path.  Lengths up to
+    # 3 MB give several tiles per request; empty, 15-byte and wrapping
+    # requests are mixed in.
+    torch = torch_cuda()
+    reqs = small_mix(n, 100 + n, lo=1, hi=3_000_000)
+    if n >= 5:
+        reqs[1].length = 0
+        reqs[2].length = 15
+        reqs[3].ctr0 = 0xFFFFFF00
+    reqs[-1].length = 0 if n == 9 else reqs[-1].length
+    b = Batch(torch, reqs, misalign=misalign, seed=n)
+    for cfg in (None, lib().batch_cfg(tile_bytes=2048, grid=3)):
+        b.dst.zero_()
+        b.run(cfg=cfg)
+        torch.cuda.synchronize()
+        for i in range(n):
+            if reqs[i].length:
+                b.check_full(i)
+
+
 def test_unaligned_and_in_place():
     torch = torch_cuda()
     reqs = small_mix(80, 13, lo=1, hi=50_000)
