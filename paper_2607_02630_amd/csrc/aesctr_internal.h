@@ -131,13 +131,15 @@ int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int wg, int bpl
 // Host side of the batch path (batch.cpp).  make_batch_record expands one
 // validated request into its device record; launch_records stages up to any
 // number of records (kMaxBatch per launch) on the (device, stream) context and
-// launches them, through the per-slot captured graph or a plain copy+launch.
+// launches them, through the per-slot captured graph or a plain copy+launch,
+// or, with allow_small and at most kSmallBatch records, in the kernel's
+// argument block.
 int check_desc(const aes_ctr_desc_t &d);
 // Tile size for a batch of batch_bytes payload bytes (2-64 KiB, multiple of 2 KiB).
 uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus);
 void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o);
 int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
-                   int bpl, bool use_graph);
+                   int bpl, bool use_graph, bool allow_small);
 
 // Defaults before tuning, per variant and size.
 Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &di);

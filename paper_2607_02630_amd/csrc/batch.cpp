@@ -203,9 +203,9 @@ int launch_small(hipStream_t st, size_t n, uint32_t tile_blocks, int grid, int b
 
 template <class Fill>
 int launch_filled(int device, hipStream_t st, size_t n, int tile_bytes, int grid, int bpl, bool use_graph,
-                  Fill fill)
+                  bool allow_small, Fill fill)
 {
-    if (n <= kSmallBatch)
+    if (allow_small && n <= kSmallBatch)
         return launch_small(st, n, static_cast<uint32_t>(tile_bytes / 16), grid, bpl, fill);
     int rc;
     BatchCtx *c = get_ctx(device, st, &rc);
@@ -298,9 +298,9 @@ int check_desc(const aes_ctr_desc_t &d)
 }
 
 int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
-                   int bpl, bool use_graph)
+                   int bpl, bool use_graph, bool allow_small)
 {
-    return launch_filled(device, st, n, tile_bytes, grid, bpl, use_graph,
+    return launch_filled(device, st, n, tile_bytes, grid, bpl, use_graph, allow_small,
                          [recs](BatchDesc *dst, size_t first, size_t m) {
                              memcpy(dst, recs + first, m * sizeof(BatchDesc));
                          });
@@ -379,7 +379,7 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
     if (sh.tile_bytes == 0)
         sh.tile_bytes = static_cast<int>(batch_tile_bytes(total_bytes, di.num_cus));
     // Records are built straight into the pinned staging slot.
-    return launch_filled(di.ordinal, st, n, sh.tile_bytes, sh.grid, sh.bpl, sh.use_graph != 0,
+    return launch_filled(di.ordinal, st, n, sh.tile_bytes, sh.grid, sh.bpl, sh.use_graph != 0, true,
                          [desc](BatchDesc *dst, size_t first, size_t m) {
                              for (size_t i = 0; i < m; ++i)
                                  make_batch_record(desc[first + i], dst + i);

@@ -123,8 +123,13 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
         uint64_t grid = tiles < cus ? tiles : cus;
         if (grid < 1)
             grid = 1;
+        // Small batches go in the kernel arguments (no upload ahead of the
+        // launch) except for zero-copy buffers: there the upload's delay
+        // lets more requests join each launch, and launches of a few
+        // requests kept too little PCIe traffic in flight (at 90% of
+        // saturation the p99 rose from 2.5 to 4.3 ms).
         rc = aesctr::launch_records(e->device, e->streams[s], recs.data(), recs.size(), static_cast<int>(tile),
-                                    static_cast<int>(grid), 2, false);
+                                    static_cast<int>(grid), 2, false, e->host_buffers == 0);
         if (rc != AES_OK)
             return drain_after_error(e, s, rc);
         *launched = true;
