@@ -111,14 +111,19 @@ typedef enum {
  *   blocks_per_lane  16-byte blocks one lane handles per loop step (1, 2, 4)
  *   wg_size          threads per workgroup (multiple of 64, <= 1024)
  *   grid             workgroups launched (persistent grid-stride loop)
- *   lds_copies       T-table replication (32 or 64 copies), T-table only */
+ *   lds_copies       T-table replication (32 or 64 copies per table), T-table only
+ *   lds_tables       T-tables held in LDS, T-table only: 4 (T0..T3, 32 copies,
+ *                    128 KiB) or 2 (T0 and T2, T1 and T3 by rotation: 32
+ *                    copies in 64 KiB, or 64 copies in 128 KiB).  64 copies
+ *                    imply 2 tables; 64 copies of 4 tables is AES_EINVAL. */
 typedef struct {
     int32_t variant;
     int32_t blocks_per_lane;
     int32_t wg_size;
     int32_t grid;
     int32_t lds_copies;
-    int32_t reserved[3];
+    int32_t lds_tables;
+    int32_t reserved[2];
 } aes_launch_cfg_t;
 
 /* aes_ctr_crypt with an explicit launch shape (cfg may be NULL = defaults).
@@ -132,7 +137,7 @@ int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[12], uint32_
  * this key size and cfg (NULL = defaults): the default shape, or the tune
  * cache's entry for the nearest size, overridden by cfg's non-zero fields,
  * with the grid clamped to the work.  All fields of *out are set (variant 1
- * or 2, never AUTO; lds_copies 0 for the bitsliced kernel).  Host only; it
+ * or 2, never AUTO; lds_copies and lds_tables 0 for the bitsliced kernel).  Host only; it
  * needs the current device's CU count.  Errors: AES_EINVAL (null out, key
  * size not 128/256, bad cfg), AES_EDEVICE. */
 int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_cfg_t *cfg, aes_launch_cfg_t *out);

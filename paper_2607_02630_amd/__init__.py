@@ -80,10 +80,10 @@ def _nonce(nonce: bytes) -> bytes:
 
 
 def launch_cfg(variant: int = 0, blocks_per_lane: int = 0, wg_size: int = 0, grid: int = 0,
-               lds_copies: int = 0) -> aes_launch_cfg_t:
+               lds_copies: int = 0, lds_tables: int = 0) -> aes_launch_cfg_t:
     c = aes_launch_cfg_t()
-    c.variant, c.blocks_per_lane, c.wg_size, c.grid, c.lds_copies = (
-        variant, blocks_per_lane, wg_size, grid, lds_copies)
+    c.variant, c.blocks_per_lane, c.wg_size, c.grid, c.lds_copies, c.lds_tables = (
+        variant, blocks_per_lane, wg_size, grid, lds_copies, lds_tables)
     return c
 
 
@@ -159,7 +159,7 @@ def launch_shape(key_bits: int, length: int, cfg: aes_launch_cfg_t | None = None
     _check(lib.aes_ctr_launch_shape(key_bits, length, ctypes.byref(cfg) if cfg is not None else None,
                                     ctypes.byref(out)), "aes_ctr_launch_shape")
     return {"variant": out.variant, "blocks_per_lane": out.blocks_per_lane, "wg_size": out.wg_size,
-            "grid": out.grid, "lds_copies": out.lds_copies}
+            "grid": out.grid, "lds_copies": out.lds_copies, "lds_tables": out.lds_tables}
 
 
 def make_sha_desc_array(items) -> ctypes.Array:

@@ -35,8 +35,10 @@ def _golden():
 
 def candidates(variant: int, quick: bool):
     if variant == 1:
-        for c, b, w in itertools.product((32, 64), (1, 2, 4), (512, 1024) if quick else (256, 512, 1024)):
-            yield dict(variant=1, lds_copies=c, blocks_per_lane=b, wg_size=w, grid=0)
+        # LDS layouts (copies, tables): four tables x 32, two x 64, two x 32.
+        for (c, t), b, w in itertools.product(((32, 4), (64, 2), (32, 2)), (1, 2, 4),
+                                              (512, 1024) if quick else (256, 512, 1024)):
+            yield dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w, grid=0)
     else:
         for w, gm in itertools.product((64, 128, 256), (1, 2, 4)):
             yield dict(variant=2, wg_size=w, grid=gm)
@@ -107,7 +109,7 @@ def main(argv=None):
                 entry = {"variant": variant, "key_bits": bits, "size_log2": int(math.log2(size)),
                          "bpl": kw.get("blocks_per_lane", 1), "wg": kw["wg_size"],
                          "grid_per_cu": kw["grid"] if variant == 2 else 1,
-                         "copies": kw.get("lds_copies", 0)}
+                         "copies": kw.get("lds_copies", 0), "tables": kw.get("lds_tables", 0)}
                 entries.append(entry)
                 report.append({**entry, "us": round(ms * 1e3, 3), "gbps": round(size / ms / 1e6, 1)})
                 print(json.dumps(report[-1]), flush=True)

@@ -36,7 +36,8 @@ struct Shape {
     int bpl;            // 16-byte blocks per lane per loop step
     int wg;             // threads per workgroup
     int grid;           // workgroups
-    int copies;         // T-table replication (32 or 64)
+    int copies;         // T-table replication (32 or 64 copies per table)
+    int tables;         // T-tables in LDS: 4 (T0..T3) or 2 (T0, T2)
 };
 
 // Arguments of the single-buffer kernels (passed by value in the kernarg

@@ -99,32 +99,42 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         sh.bpl = te.bpl;
         sh.wg = te.wg;
         sh.copies = te.copies;
+        sh.tables = te.tables ? te.tables : (te.copies == 64 ? 2 : 4);
         sh.grid = te.grid_per_cu * di.num_cus;
     } else if (sh.variant == AES_VARIANT_TTABLE) {
-        // One workgroup per CU with the 32-copy table.  The chunk a
-        // workgroup takes per step (workgroup size x blocks per lane) is the
-        // largest that still gives every CU at least one: a larger chunk
-        // leaves CUs idle (4 MiB with 2048-block chunks runs at half the
-        // speed of 2 MiB), a smaller one adds steps.  Measured on MI355X: 512
-        // threads x 1 block up to 2 MiB, 1024 x 1 at 4 MiB, 1024 x 2 at 8-16
+        // One workgroup per CU.  The chunk a workgroup takes per step
+        // (workgroup size x blocks per lane) is the largest that still gives
+        // every CU at least one: a larger chunk leaves CUs idle (4 MiB with
+        // 2048-block chunks runs at half the speed of 2 MiB), a smaller one
+        // adds steps.  Up to 4 MiB the LDS holds only T0 and T2 (32 copies,
+        // 64 KiB): half the table fill, which is a large part of a short
+        // launch, for about 15% more VALU work per block.  Measured on
+        // MI355X (kernel-only, per launch): AES-128 1 MiB 3.72 us against
+        // 4.04 with four tables, 4 MiB 5.32 against 5.53, 8 MiB 8.23 against
+        // 8.14 (so four tables from 8 MiB on); AES-256 1 MiB 4.11 against
+        // 4.57 (256 threads).  Shapes: 512 threads x 1 block up to 2 MiB
+        // (256 for AES-256 up to 1 MiB), 512 x 2 at 4 MiB, 1024 x 2 at 8-16
         // MiB, 1024 x 4 from 64 MiB (two blocks per lane are within 3% at 16
         // MiB, four within 7% at 64 MiB, for either key size).
         sh.grid = di.num_cus;
         sh.copies = 32;
         const uint64_t per_cu = (len / 16) / static_cast<uint64_t>(di.num_cus > 0 ? di.num_cus : 1);
         if (per_cu >= 8192) {
-            sh.bpl = 4; sh.wg = 1024;
+            sh.bpl = 4; sh.wg = 1024; sh.tables = 4;
         } else if (per_cu >= 2048) {
-            sh.bpl = 2; sh.wg = 1024;
+            sh.bpl = 2; sh.wg = 1024; sh.tables = 4;
         } else if (per_cu >= 1024) {
-            sh.bpl = 1; sh.wg = 1024;
+            sh.bpl = 2; sh.wg = 512; sh.tables = 2;
+        } else if (per_cu >= 512 || key_bits == 128) {
+            sh.bpl = 1; sh.wg = 512; sh.tables = 2;
         } else {
-            sh.bpl = 1; sh.wg = 512;
+            sh.bpl = 1; sh.wg = 256; sh.tables = 2;
         }
     } else {
         sh.bpl = 1;
         sh.wg = 256;
         sh.copies = 0;
+        sh.tables = 0;
         sh.grid = 2 * di.num_cus;
     }
     return sh;
@@ -188,6 +198,10 @@ int check_cfg(const aes_launch_cfg_t *cfg, int *variant)
             return AES_EINVAL;
         if (cfg->grid < 0 || (cfg->lds_copies != 0 && cfg->lds_copies != 32 && cfg->lds_copies != 64))
             return AES_EINVAL;
+        if (cfg->lds_tables != 0 && cfg->lds_tables != 2 && cfg->lds_tables != 4)
+            return AES_EINVAL;
+        if (cfg->lds_copies == 64 && cfg->lds_tables == 4)   // 256 KiB: more than a CU's LDS
+            return AES_EINVAL;
     }
     return AES_OK;
 }
@@ -202,6 +216,14 @@ Shape resolve_shape(int variant, int key_bits, uint64_t len, const aes_launch_cf
         if (cfg->wg_size) sh.wg = cfg->wg_size;
         if (cfg->grid) sh.grid = cfg->grid;
         if (cfg->lds_copies) sh.copies = cfg->lds_copies;
+        if (cfg->lds_tables) sh.tables = cfg->lds_tables;
+    }
+    // 64 copies exist only of two tables; a T-table shape always names both.
+    if (sh.variant == AES_VARIANT_TTABLE) {
+        if (sh.copies == 64)
+            sh.tables = 2;
+        else if (sh.tables == 0)
+            sh.tables = 4;
     }
     clamp_grid(&sh, len);
     return sh;
@@ -227,6 +249,7 @@ extern "C" int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_c
     out->wg_size = sh.wg;
     out->grid = sh.grid;
     out->lds_copies = sh.copies;
+    out->lds_tables = sh.tables;
     return AES_OK;
 }
 

@@ -18,7 +18,7 @@ namespace aesctr {
 namespace {
 
 constexpr int kBatchWG = 1024;
-constexpr int kBatchCopies = 32;
+constexpr int kBatchLayout = kLayout4x32;
 
 // Request pointers arrive as integers; these types keep their accesses in the
 // global address space (global_load/store rather than flat).
@@ -31,7 +31,7 @@ typedef __attribute__((address_space(1))) uint8_t g_u8;
 // lane (the round-1/2 sharing needs the whole wave), and lane i of each step
 // holds block s0 + 64*b + i.
 template <int NR, int BPL, bool ALIGNED>
-__device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const CtrArgs &a, uint64_t b0,
+__device__ __forceinline__ void run_tile(const TTable<kBatchLayout> &tt, const CtrArgs &a, uint64_t b0,
                                          uint64_t b1, uint32_t lane)
 {
     const uint64_t nfull = a.len >> 4;
@@ -56,7 +56,7 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const C
             }
         }
         const WaveGroups w = wave_groups<BPL>(a, a.ctr0 + static_cast<uint32_t>(s0));
-        keystream_wave<NR, kBatchCopies, BPL>(tt, a, krot, ctr, w, ks);
+        keystream_wave<NR, kBatchLayout, BPL>(tt, a, krot, ctr, w, ks);
 #pragma unroll
         for (int b = 0; b < BPL; ++b) {
             const uint64_t idx = s0 + 64 * b + lane;
@@ -90,7 +90,7 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchCopies> &tt, const C
 // kernel arguments; both wave-uniform, so their fields arrive by scalar
 // loads): the request's key material and pointers, then the tile's blocks.
 template <int BPL, class Rec>
-__device__ __forceinline__ void request_tile(const TTable<kBatchCopies> &tt, const Rec &R, uint32_t t,
+__device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, const Rec &R, uint32_t t,
                                              uint32_t tile_blocks, uint32_t lane)
 {
     CtrArgs a;
@@ -140,14 +140,14 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
     const uint32_t tile_blocks = hdr->tile_blocks;
 
     uint32_t tv[kFillStores / kBatchWG];
-    fill_read<kBatchWG>(tv);
+    fill_read<kBatchLayout, kBatchWG>(tv);
     for (uint32_t i = threadIdx.x; i < n; i += kBatchWG)
         s_tile0[i] = desc[i].tile0;
-    fill_write<kBatchCopies, kBatchWG>(lds, tv);
+    fill_write<kBatchLayout, kBatchWG>(lds, tv);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63;
-    TTable<kBatchCopies> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
+    TTable<kBatchLayout> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
 
     // Tile claiming.  The launch's W waves first take tiles 0..W-1 statically,
     // spread so that consecutive tiles land on different CUs (wave j of
@@ -188,12 +188,12 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_small_kernel(const SmallBa
     __shared__ uint32_t lds[kLdsWords];
 
     uint32_t tv[kFillStores / kBatchWG];
-    fill_read<kBatchWG>(tv);
-    fill_write<kBatchCopies, kBatchWG>(lds, tv);
+    fill_read<kBatchLayout, kBatchWG>(tv);
+    fill_write<kBatchLayout, kBatchWG>(lds, tv);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63;
-    TTable<kBatchCopies> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
+    TTable<kBatchLayout> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
     const uint32_t waves = gridDim.x * (kBatchWG / 64);
     const uint32_t n = args.n;
     for (uint32_t t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * gridDim.x + blockIdx.x;

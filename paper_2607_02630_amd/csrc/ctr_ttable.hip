@@ -52,8 +52,8 @@ __device__ __forceinline__ void prefetch(const u32x4 *src, uint64_t start, uint3
     }
 }
 
-template <int NR, int COPIES, int BPL, bool ALIGNED>
-__device__ __forceinline__ void chunk_step(const TTable<COPIES> &tt, const CtrArgs &a, const uint32_t *krot,
+template <int NR, int LAYOUT, int BPL, bool ALIGNED>
+__device__ __forceinline__ void chunk_step(const TTable<LAYOUT> &tt, const CtrArgs &a, const uint32_t *krot,
                                            uint64_t start, uint64_t chunk, uint32_t wave, uint32_t lane,
                                            uint64_t nfull, const WaveGroups &w, const u32x4 (&d)[BPL])
 {
@@ -61,7 +61,7 @@ __device__ __forceinline__ void chunk_step(const TTable<COPIES> &tt, const CtrAr
 #pragma unroll
     for (int b = 0; b < BPL; ++b)
         ctr[b] = a.ctr0 + static_cast<uint32_t>(block_of<BPL>(start, wave, lane, b));
-    keystream_wave<NR, COPIES, BPL>(tt, a, krot, ctr, w, ks);
+    keystream_wave<NR, LAYOUT, BPL>(tt, a, krot, ctr, w, ks);
     if (start + chunk <= nfull) {
 #pragma unroll
         for (int b = 0; b < BPL; ++b)
@@ -84,10 +84,10 @@ __device__ __forceinline__ uint32_t first_ctr(const CtrArgs &a, uint64_t start, 
     return a.ctr0 + static_cast<uint32_t>(start + 64u * wave * BPL);
 }
 
-template <int NR, int COPIES, int BPL, int WG, bool ALIGNED>
+template <int NR, int LAYOUT, int BPL, int WG, bool ALIGNED>
 __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
 {
-    __shared__ uint32_t lds[kLdsWords];
+    __shared__ uint32_t lds[layout_lds_words(LAYOUT)];
 
     const uint64_t nfull = a.len >> 4;
     const uint64_t wg = WG;
@@ -104,16 +104,16 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t chunk = wg * BPL;
     uint32_t tv[kFillStores / WG];
-    fill_read<WG>(tv);
+    fill_read<LAYOUT, WG>(tv);
     const uint64_t last = nfull ? nfull - 1 : 0;
     const u32x4 *src = nfull ? reinterpret_cast<const u32x4 *>(a.in) : &g_dummy_block;
     u32x4 d[BPL];
     prefetch<ALIGNED, BPL>(src, start, wave, lane, nfull, last, d);
-    fill_write<COPIES, WG>(lds, tv);
+    fill_write<LAYOUT, WG>(lds, tv);
     __syncthreads();
 
-    const uint32_t k = COPIES == 32 ? (lane & 31) : lane;
-    TTable<COPIES> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
+    const uint32_t k = LAYOUT == kLayout2x64 ? lane : (lane & 31);
+    TTable<LAYOUT> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
 
     // Group constants of the first chunk: wave 0 computes every group the
     // workgroup's chunk touches (one lane each, from the LDS tables) and the
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
 
     // rotr(rk, 8) for the two-table fold; uniform, lives in scalar registers.
     uint32_t krot[60];
-    if constexpr (COPIES == 64) {
+    if constexpr (LAYOUT != kLayout4x32) {
 #pragma unroll
         for (int i = 0; i < 4 * (NR + 1); ++i) krot[i] = (a.rk[i] >> 8) | (a.rk[i] << 24);
     }
@@ -158,18 +158,18 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     u32x4 e[BPL];
     if (start < nfull) {
         prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, e);
-        chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
+        chunk_step<NR, LAYOUT, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
         start += step;
         while (start < nfull) {
             prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, d);
             w = wave_groups<BPL>(a, first_ctr<BPL>(a, start, wave));
-            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, e);
+            chunk_step<NR, LAYOUT, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, e);
             start += step;
             if (!(start < nfull))
                 break;
             prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, e);
             w = wave_groups<BPL>(a, first_ctr<BPL>(a, start, wave));
-            chunk_step<NR, COPIES, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
+            chunk_step<NR, LAYOUT, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
             start += step;
         }
     }
@@ -179,43 +179,43 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     if (tail != 0 && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         uint32_t ctr1[1] = {a.ctr0 + static_cast<uint32_t>(nfull)};
         uint32_t ks[1][4];
-        keystream<NR, COPIES, 1>(tt, a, krot, ctr1, ks);
+        keystream<NR, LAYOUT, 1>(tt, a, krot, ctr1, ks);
         const uint64_t off = 16 * nfull;
         for (uint32_t i = 0; i < tail; ++i)
             a.out[off + i] = a.in[off + i] ^ static_cast<uint8_t>(ks[0][i >> 2] >> (8 * (i & 3)));
     }
 }
 
-template <int NR, int COPIES, int BPL, int WG>
+template <int NR, int LAYOUT, int BPL, int WG>
 int launch_w(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
     (void)hipGetLastError();   // not ours: left by earlier calls
     if (aligned)
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, COPIES, BPL, WG, true>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true>), dim3(sh.grid), dim3(WG), 0, st, a);
     else
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, COPIES, BPL, WG, false>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, false>), dim3(sh.grid), dim3(WG), 0, st, a);
     return launch_status();
 }
 
-template <int NR, int COPIES, int BPL>
+template <int NR, int LAYOUT, int BPL>
 int launch_t(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     switch (sh.wg) {
-    case 256: return launch_w<NR, COPIES, BPL, 256>(a, sh, st);
-    case 512: return launch_w<NR, COPIES, BPL, 512>(a, sh, st);
-    case 1024: return launch_w<NR, COPIES, BPL, 1024>(a, sh, st);
+    case 256: return launch_w<NR, LAYOUT, BPL, 256>(a, sh, st);
+    case 512: return launch_w<NR, LAYOUT, BPL, 512>(a, sh, st);
+    case 1024: return launch_w<NR, LAYOUT, BPL, 1024>(a, sh, st);
     default: return AES_EINVAL;
     }
 }
 
-template <int NR, int COPIES>
+template <int NR, int LAYOUT>
 int launch_b(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     switch (sh.bpl) {
-    case 1: return launch_t<NR, COPIES, 1>(a, sh, st);
-    case 2: return launch_t<NR, COPIES, 2>(a, sh, st);
-    case 4: return launch_t<NR, COPIES, 4>(a, sh, st);
+    case 1: return launch_t<NR, LAYOUT, 1>(a, sh, st);
+    case 2: return launch_t<NR, LAYOUT, 2>(a, sh, st);
+    case 4: return launch_t<NR, LAYOUT, 4>(a, sh, st);
     default: return AES_EINVAL;
     }
 }
@@ -227,10 +227,24 @@ int launch_ctr_ttable(const CtrArgs &a, int nr, const Shape &sh, hipStream_t st)
     // The LDS fill splits 8192 stores evenly over the workgroup.
     if ((sh.wg != 256 && sh.wg != 512 && sh.wg != 1024) || sh.grid <= 0)
         return AES_EINVAL;
+    // (copies, tables): (32, 4), (64, 2) or (32, 2).
+    int layout;
+    if (sh.copies == 32 && sh.tables == 4)
+        layout = kLayout4x32;
+    else if (sh.copies == 64 && sh.tables == 2)
+        layout = kLayout2x64;
+    else if (sh.copies == 32 && sh.tables == 2)
+        layout = kLayout2x32;
+    else
+        return AES_EINVAL;
     if (nr == 10)
-        return sh.copies == 64 ? launch_b<10, 64>(a, sh, st) : sh.copies == 32 ? launch_b<10, 32>(a, sh, st) : AES_EINVAL;
+        return layout == kLayout4x32 ? launch_b<10, kLayout4x32>(a, sh, st)
+             : layout == kLayout2x64 ? launch_b<10, kLayout2x64>(a, sh, st)
+                                     : launch_b<10, kLayout2x32>(a, sh, st);
     if (nr == 14)
-        return sh.copies == 64 ? launch_b<14, 64>(a, sh, st) : sh.copies == 32 ? launch_b<14, 32>(a, sh, st) : AES_EINVAL;
+        return layout == kLayout4x32 ? launch_b<14, kLayout4x32>(a, sh, st)
+             : layout == kLayout2x64 ? launch_b<14, kLayout2x64>(a, sh, st)
+                                     : launch_b<14, kLayout2x32>(a, sh, st);
     return AES_EINVAL;
 }
 

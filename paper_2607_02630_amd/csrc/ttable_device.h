@@ -10,13 +10,19 @@
 //
 // Random table indices would serialise on LDS banks, so every lane reads its
 // own bank-resident copy.  The entry for index x sits at byte 256*x, and the
-// lane's copy at +4*k (k = lane mod COPIES): the address is built by one
-// v_perm_b32 that drops the state byte into bits 8..15 next to the lane's
-// constant bits.
-//   COPIES == 32: T0|T1 interleaved in [0, 64 KiB) (T1 at +128 B), T2|T3 in
-//                 [64 KiB, 128 KiB).  Lanes l and l+32 share a bank.
-//   COPIES == 64: T0 in [0, 64 KiB), T2 in [64 KiB, 128 KiB); T1 = rotl(T0, 8)
-//                 and T3 = rotl(T2, 8) are folded into one rotate per column.
+// lane's copy at +4*k (k = lane mod the copy count): the address is built by
+// one v_perm_b32 that drops the state byte into bits 8..15 next to the lane's
+// constant bits.  Three layouts (the kernels' LAYOUT parameter):
+//   kLayout4x32: 32 copies of each of T0..T3 (128 KiB): T0|T1 interleaved in
+//                [0, 64 KiB) (T1 at +128 B), T2|T3 in [64 KiB, 128 KiB).
+//                Lanes l and l+32 share a bank.
+//   kLayout2x64: 64 copies of T0 in [0, 64 KiB) and of T2 in [64 KiB,
+//                128 KiB); T1 = rotl(T0, 8) and T3 = rotl(T2, 8) are folded
+//                into one rotate per column.
+//   kLayout2x32: 32 copies of T0 and of T2, interleaved in [0, 64 KiB) (T2 at
+//                +128 B), with the same fold: half the table fill of the other
+//                two for about 15% more VALU work per block, which pays for
+//                launches short enough that the fill is a large part of them.
 #pragma once
 
 #include "aes_tables.h"
@@ -48,6 +54,11 @@ constexpr RoundTables build_round_tables()
 __constant__ RoundTables c_round = build_round_tables();
 
 constexpr int kLdsWords = 32768;   // 128 KiB
+
+enum : int { kLayout4x32 = 0, kLayout2x64 = 1, kLayout2x32 = 2 };
+
+// LDS words a layout occupies.
+constexpr int layout_lds_words(int layout) { return layout == kLayout2x32 ? kLdsWords / 2 : kLdsWords; }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -82,76 +93,90 @@ __device__ __forceinline__ uint32_t lds_at(const char *lds, uint32_t byte_addr)
     return *reinterpret_cast<const uint32_t *>(lds + byte_addr);
 }
 
-// The LDS image is 8192 16-byte stores (128 KiB).  Thread t performs
-// stores w = t + u*WG, u < 8192/WG, each a 4-way broadcast of one table
-// entry.  The entries are read from the constant table first (fill_read) so
-// the caller can issue its own global loads before the table reads are
-// waited for; fill_write then stores them.
+// The LDS image is fill_stores(LAYOUT) 16-byte stores: 8192 (128 KiB), or
+// 4096 (64 KiB) for kLayout2x32.  Thread t performs stores w = t + u*WG, each
+// a 4-way broadcast of one table entry (a run of four copies).  The entries
+// are read from the constant table first (fill_read) so the caller can issue
+// its own global loads before the table reads are waited for; fill_write then
+// stores them.
 constexpr int kFillStores = 8192;
 
-template <int WG>
+constexpr int fill_stores(int layout) { return layout == kLayout2x32 ? kFillStores / 2 : kFillStores; }
+
+template <int LAYOUT, int WG>
 __device__ __forceinline__ void fill_read(uint32_t (&tv)[kFillStores / WG])
 {
+    // Stores per table entry: 32 (four tables or 64 copies), 16 (kLayout2x32).
+    constexpr int shift = LAYOUT == kLayout2x32 ? 4 : 5;
 #pragma unroll
-    for (int u = 0; u < kFillStores / WG; ++u)
-        tv[u] = c_tables.t0[(threadIdx.x + u * WG) >> 5];
+    for (int u = 0; u < fill_stores(LAYOUT) / WG; ++u)
+        tv[u] = c_tables.t0[(threadIdx.x + u * WG) >> shift];
 }
 
-template <int COPIES, int WG>
+template <int LAYOUT, int WG>
 __device__ __forceinline__ void fill_write(uint32_t *lds, const uint32_t (&tv)[kFillStores / WG])
 {
 #pragma unroll
-    for (int u = 0; u < kFillStores / WG; ++u) {
+    for (int u = 0; u < fill_stores(LAYOUT) / WG; ++u) {
         const uint32_t w = threadIdx.x + u * WG;
-        const uint32_t i = w >> 5;
         uint32_t val, addr;
-        if constexpr (COPIES == 32) {
-            const uint32_t q = w & 7, t = (w >> 3) & 3;
+        if constexpr (LAYOUT == kLayout4x32) {
+            const uint32_t i = w >> 5, q = w & 7, t = (w >> 3) & 3;
             val = rotl32(tv[u], 8 * t);
             addr = (t >> 1) * 65536 + i * 256 + (t & 1) * 128 + q * 16;
-        } else {
-            const uint32_t q = w & 15, t2 = (w >> 4) & 1;
+        } else if constexpr (LAYOUT == kLayout2x64) {
+            const uint32_t i = w >> 5, q = w & 15, t2 = (w >> 4) & 1;
             val = t2 ? rotl32(tv[u], 16) : tv[u];
             addr = t2 * 65536 + i * 256 + q * 16;
+        } else {
+            const uint32_t i = w >> 4, q = w & 7, t2 = (w >> 3) & 1;
+            val = t2 ? rotl32(tv[u], 16) : tv[u];
+            addr = i * 256 + t2 * 128 + q * 16;
         }
         *reinterpret_cast<u32x4 *>(reinterpret_cast<char *>(lds) + addr) = u32x4{val, val, val, val};
     }
 }
 
-template <int COPIES>
+// lb0 / lb1: the lane's copy offset 4*k for the first / second 64 KiB
+// (lb1 = lb0 | 64 KiB; unused by kLayout2x32).
+template <int LAYOUT>
 struct TTable {
     const char *lds;
-    uint32_t lb0, lb1;   // lane bits for region 0 / region 1
+    uint32_t lb0, lb1;
 
     // T_t[byte R of v] for t = 0..3.
     template <int T, int R>
     __device__ __forceinline__ uint32_t get(uint32_t v) const
     {
-        uint32_t a = taddr<R>(v, (T >= 2) ? lb1 : lb0);
-        if constexpr (COPIES == 32) {
+        if constexpr (LAYOUT == kLayout4x32) {
+            const uint32_t a = taddr<R>(v, (T >= 2) ? lb1 : lb0);
             return lds_at(lds, a + ((T & 1) ? 128u : 0u));
         } else {
-            uint32_t e = lds_at(lds, a);
+            const uint32_t e = raw<(T >= 2) ? 1 : 0, R>(v);
             return (T & 1) ? rotl8(e) : e;
         }
     }
 
-    // Raw region entries (T0 or T2 region) without the odd-table rotation.
+    // Raw entries of the T0 (REGION 0) or T2 (REGION 1) table, without the
+    // odd tables' rotation.
     template <int REGION, int R>
     __device__ __forceinline__ uint32_t raw(uint32_t v) const
     {
-        return lds_at(lds, taddr<R>(v, REGION ? lb1 : lb0));
+        if constexpr (LAYOUT == kLayout2x32)
+            return lds_at(lds, taddr<R>(v, lb0) + (REGION ? 128u : 0u));
+        else
+            return lds_at(lds, taddr<R>(v, REGION ? lb1 : lb0));
     }
 
-    // One full round: s -> o with round key words k[0..3]; rk_rot holds
-    // rotr(k, 8) for the COPIES == 64 fold.
+    // One full round: s -> o with round key words k[0..3]; krot holds
+    // rotr(k, 8) for the two-table fold.
     __device__ __forceinline__ void round(const uint32_t s[4], uint32_t o[4],
                                           const uint32_t *k, const uint32_t *krot) const
     {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const uint32_t s0 = s[c], s1 = s[(c + 1) & 3], s2 = s[(c + 2) & 3], s3 = s[(c + 3) & 3];
-            if constexpr (COPIES == 32) {
+            if constexpr (LAYOUT == kLayout4x32) {
                 o[c] = xor3(xor3(get<0, 0>(s0), get<1, 1>(s1), get<2, 2>(s2)), get<3, 3>(s3), k[c]);
             } else {
                 // T1[b]^T3[d]^k = rotl8(T0[b]^T2[d]^rotr8(k))
@@ -182,8 +207,8 @@ struct TTable {
 // Keystreams of N counter blocks, computed round by round across the N
 // blocks so their independent lookups interleave.  ctr[i] is already
 // ctr0 + j mod 2^32.
-template <int NR, int COPIES, int N>
-__device__ __forceinline__ void keystream(const TTable<COPIES> &tt, const CtrArgs &a,
+template <int NR, int LAYOUT, int N>
+__device__ __forceinline__ void keystream(const TTable<LAYOUT> &tt, const CtrArgs &a,
                                           const uint32_t *krot, const uint32_t *ctr, uint32_t (*ks)[4])
 {
     uint32_t s[N][4], o[N][4];
@@ -253,8 +278,8 @@ __device__ __forceinline__ void group_consts(const CtrArgs &a, uint32_t g, uint3
 // chunk of a launch has every wave of a workgroup start at once, and one
 // wave computing all of the workgroup's groups (a lane each) costs less than
 // sixteen waves queueing on the CU's one scalar unit.
-template <int COPIES>
-__device__ __forceinline__ void group_consts_lds(const TTable<COPIES> &tt, const CtrArgs &a, uint32_t g,
+template <int LAYOUT>
+__device__ __forceinline__ void group_consts_lds(const TTable<LAYOUT> &tt, const CtrArgs &a, uint32_t g,
                                                  uint32_t G[4])
 {
     const uint32_t s1 = a.k1[1] ^ tt.template get<2, 0>(g ^ (a.x0 >> 16));
@@ -296,8 +321,8 @@ __device__ __forceinline__ WaveGroups wave_groups(const CtrArgs &a, uint32_t fir
 // Keystream of N blocks per lane, lane i / block b holding counter
 // first + 64 b + i where w = wave_groups<N>(a, first).  Every lane of the
 // wave must be active.
-template <int NR, int COPIES, int N>
-__device__ __forceinline__ void keystream_wave(const TTable<COPIES> &tt, const CtrArgs &a, const uint32_t *krot,
+template <int NR, int LAYOUT, int N>
+__device__ __forceinline__ void keystream_wave(const TTable<LAYOUT> &tt, const CtrArgs &a, const uint32_t *krot,
                                                const uint32_t *ctr, const WaveGroups &w, uint32_t (*ks)[4])
 {
     uint32_t s[N][4], o[N][4];

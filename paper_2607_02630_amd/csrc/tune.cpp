@@ -59,6 +59,7 @@ void parse(const std::string &text)
             else if (name == "wg") e.wg = static_cast<int>(v);
             else if (name == "grid_per_cu") e.grid_per_cu = static_cast<int>(v);
             else if (name == "copies") e.copies = static_cast<int>(v);
+            else if (name == "tables") e.tables = static_cast<int>(v);
             else if (name == "tile_bytes") e.tile_bytes = static_cast<int>(v);
             q = colon + 1;
         }
@@ -102,7 +103,8 @@ bool tune_lookup(int variant, int key_bits, uint64_t len, TuneEntry *out)
     for (const TuneEntry &e : g_entries) {
         if (e.variant != variant || e.key_bits != key_bits)
             continue;
-        if (e.variant == 1 && e.copies != 32 && e.copies != 64)
+        if (e.variant == 1 && ((e.copies != 32 && e.copies != 64) || (e.tables != 0 && e.tables != 2 && e.tables != 4) ||
+                               (e.copies == 64 && e.tables == 4)))
             continue;
         if (!best || abs(e.size_log2 - want) < abs(best->size_log2 - want))
             best = &e;

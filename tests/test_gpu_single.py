@@ -42,14 +42,15 @@ def gpu_crypt(key: bytes, nonce: bytes, ctr0: int, data: np.ndarray, cfg=None,
     return to_host(dst)
 
 
-TT_SHAPES = [dict(variant=1, lds_copies=c, blocks_per_lane=b, wg_size=w)
-             for c in (32, 64) for b in (1, 2, 4) for w in (256, 1024)]
+# Every LDS layout (copies, tables): four tables x 32, two x 64, two x 32.
+TT_SHAPES = [dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w)
+             for c, t in ((32, 4), (64, 2), (32, 2)) for b in (1, 2, 4) for w in (256, 1024)]
 BS_SHAPES = [dict(variant=2, wg_size=w) for w in (64, 256)]
 SHAPES = TT_SHAPES + BS_SHAPES
 
 
 def shape_id(kw):
-    short = {"lds_copies": "c", "blocks_per_lane": "b", "wg_size": "w"}
+    short = {"lds_copies": "c", "lds_tables": "t", "blocks_per_lane": "b", "wg_size": "w"}
     name = "tt" if kw["variant"] == 1 else "bs"
     return name + "".join(f"-{short[k]}{v}" for k, v in kw.items() if k != "variant")
 
@@ -167,3 +168,35 @@ def test_overlap_rejected_on_device():
     rc = L.lib.aes_ctr_crypt(ctypes.byref(s), bytes(12), 1, buf.data_ptr(),
                              buf.data_ptr() + 16, 1024, torch.cuda.current_stream().cuda_stream)
     assert rc == -8
+
+
+def test_default_shapes_pick_the_lds_layout_by_size():
+    """Without a tune cache: two T-tables (64 KiB of LDS) up to 4 MiB, where
+    the table fill is a large part of a launch, four from 8 MiB on; 64
+    copies always mean two tables."""
+    import os
+    A = lib()
+    here = os.path.dirname(os.path.abspath(A.lib._name))
+    if os.environ.get("AESCTR_TUNE_CACHE") or os.path.exists(os.path.join(here, "tune_cache.json")):
+        pytest.skip("a tune cache overrides the default shapes")
+    cus = torch_cuda().cuda.get_device_properties(0).multi_processor_count
+    MiB = 1 << 20
+
+    def shape(bits, size, **kw):
+        return A.launch_shape(bits, size, A.launch_cfg(**kw) if kw else None)
+
+    # The rule works in blocks per CU; these sizes are the MI355X ones (256 CUs).
+    scale = cus / 256
+    s = shape(128, int(1 * MiB * scale))
+    assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 1), s
+    s = shape(256, int(1 * MiB * scale))
+    assert (s["lds_tables"], s["wg_size"]) == (2, 256), s
+    s = shape(128, int(4 * MiB * scale))
+    assert (s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (2, 512, 2), s
+    s = shape(128, int(8 * MiB * scale))
+    assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 4, 1024, 2), s
+    assert shape(128, MiB, lds_copies=64)["lds_tables"] == 2
+    assert shape(128, MiB, lds_tables=4)["lds_tables"] == 4
+    assert shape(128, 8 * MiB, lds_tables=2)["lds_tables"] == 2
+    s = shape(128, MiB, variant=2)
+    assert (s["lds_copies"], s["lds_tables"]) == (0, 0), s

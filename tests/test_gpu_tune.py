@@ -38,7 +38,7 @@ for e in cache["entries"]:
     assert shape["variant"] == e["variant"], (e, shape)
     assert shape["blocks_per_lane"] == e["bpl"] and shape["wg_size"] == e["wg"], (e, shape)
     if e["variant"] == 1:
-        assert shape["lds_copies"] == e["copies"], (e, shape)
+        assert shape["lds_copies"] == e["copies"] and shape["lds_tables"] == e["tables"], (e, shape)
     assert shape["grid"] <= e["grid_per_cu"] * cus, (e, shape)
     key, nonce = W.sweep_key(bits)
     x = torch.from_numpy(W.sweep_payload(size, bits)).cuda()
