@@ -35,10 +35,13 @@ def _golden():
 
 def candidates(variant: int, quick: bool):
     if variant == 1:
-        # LDS layouts (copies, tables): four tables x 32, two x 64, two x 32.
+        # LDS layouts (copies, tables): four tables x 32, two x 64, two x 32;
+        # grids of one workgroup per CU, and two or four with the 64 KiB
+        # layout (two fit in a CU's LDS).
         for (c, t), b, w in itertools.product(((32, 4), (64, 2), (32, 2)), (1, 2, 4),
                                               (512, 1024) if quick else (256, 512, 1024)):
-            yield dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w, grid=0)
+            for gm in ((1, 2, 4) if t == 2 and c == 32 else (1,)):
+                yield dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w, grid=gm)
     else:
         for w, gm in itertools.product((64, 128, 256), (1, 2, 4)):
             yield dict(variant=2, wg_size=w, grid=gm)
@@ -95,7 +98,7 @@ def main(argv=None):
                 best = None
                 for kw in candidates(variant, args.quick):
                     grid = kw.pop("grid")
-                    cfg = A.launch_cfg(grid=grid * cus if variant == 2 else 0, **kw)
+                    cfg = A.launch_cfg(grid=grid * cus, **kw)
                     A.aes_ctr_crypt(sched, nonce, 1, ins[0], outs[0], cfg=cfg)
                     torch.cuda.synchronize()
                     digest = hashlib.sha256(outs[0].cpu().numpy().tobytes()).hexdigest()
@@ -108,7 +111,7 @@ def main(argv=None):
                 ms, kw = best
                 entry = {"variant": variant, "key_bits": bits, "size_log2": int(math.log2(size)),
                          "bpl": kw.get("blocks_per_lane", 1), "wg": kw["wg_size"],
-                         "grid_per_cu": kw["grid"] if variant == 2 else 1,
+                         "grid_per_cu": kw["grid"],
                          "copies": kw.get("lds_copies", 0), "tables": kw.get("lds_tables", 0)}
                 entries.append(entry)
                 report.append({**entry, "us": round(ms * 1e3, 3), "gbps": round(size / ms / 1e6, 1)})

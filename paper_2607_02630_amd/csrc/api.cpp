@@ -102,33 +102,36 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         sh.tables = te.tables ? te.tables : (te.copies == 64 ? 2 : 4);
         sh.grid = te.grid_per_cu * di.num_cus;
     } else if (sh.variant == AES_VARIANT_TTABLE) {
-        // One workgroup per CU.  The chunk a workgroup takes per step
-        // (workgroup size x blocks per lane) is the largest that still gives
-        // every CU at least one: a larger chunk leaves CUs idle (4 MiB with
-        // 2048-block chunks runs at half the speed of 2 MiB), a smaller one
-        // adds steps.  Up to 4 MiB the LDS holds only T0 and T2 (32 copies,
-        // 64 KiB): half the table fill, which is a large part of a short
-        // launch, for about 15% more VALU work per block.  Measured on
-        // MI355X (kernel-only, per launch): AES-128 1 MiB 3.72 us against
-        // 4.04 with four tables, 4 MiB 5.32 against 5.53, 8 MiB 8.23 against
-        // 8.14 (so four tables from 8 MiB on); AES-256 1 MiB 4.11 against
-        // 4.57 (256 threads).  Shapes: 512 threads x 1 block up to 2 MiB
-        // (256 for AES-256 up to 1 MiB), 512 x 2 at 4 MiB, 1024 x 2 at 8-16
-        // MiB, 1024 x 4 from 64 MiB (two blocks per lane are within 3% at 16
-        // MiB, four within 7% at 64 MiB, for either key size).
+        // The LDS holds only T0 and T2 (32 copies, 64 KiB): half the table
+        // fill of four tables, for about 15% more VALU work per block, and
+        // room for two workgroups per CU, so one workgroup's fill and
+        // barriers overlap the other's keystream.  The chunk a workgroup
+        // takes per step (workgroup size x blocks per lane) is the largest
+        // that still gives every CU work: a larger chunk leaves CUs idle, a
+        // smaller one adds steps.  Measured on MI355X (kernel-only, per
+        // launch, against one workgroup per CU with four tables):
+        //   AES-128  1 MiB 3.72 us (4.04), 8 MiB 7.84 (8.22), 32 MiB 23.5
+        //            (26.6), 256 MiB 172.6 (174.9);
+        //   AES-256  1 MiB 4.11 us (4.57, 256 threads), 8 MiB 9.81 (10.19),
+        //            32 MiB 30.9 (37.0), 256 MiB 242 (246).
+        // Up to 4 MiB one workgroup per CU (512 threads x 1 block up to 2
+        // MiB, 256 for AES-256 up to 1 MiB, 512 x 2 at 4 MiB); from 8 MiB
+        // 512 threads x 2 blocks (x 4 from 16 MiB) with up to four
+        // workgroups per CU in the grid, two of them resident at a time.
         sh.grid = di.num_cus;
         sh.copies = 32;
+        sh.tables = 2;
         const uint64_t per_cu = (len / 16) / static_cast<uint64_t>(di.num_cus > 0 ? di.num_cus : 1);
-        if (per_cu >= 8192) {
-            sh.bpl = 4; sh.wg = 1024; sh.tables = 4;
-        } else if (per_cu >= 2048) {
-            sh.bpl = 2; sh.wg = 1024; sh.tables = 4;
+        if (per_cu >= 2048) {
+            sh.bpl = per_cu >= 4096 ? 4 : 2;
+            sh.wg = 512;
+            sh.grid = 4 * di.num_cus;
         } else if (per_cu >= 1024) {
-            sh.bpl = 2; sh.wg = 512; sh.tables = 2;
+            sh.bpl = 2; sh.wg = 512;
         } else if (per_cu >= 512 || key_bits == 128) {
-            sh.bpl = 1; sh.wg = 512; sh.tables = 2;
+            sh.bpl = 1; sh.wg = 512;
         } else {
-            sh.bpl = 1; sh.wg = 256; sh.tables = 2;
+            sh.bpl = 1; sh.wg = 256;
         }
     } else {
         sh.bpl = 1;

@@ -171,9 +171,9 @@ def test_overlap_rejected_on_device():
 
 
 def test_default_shapes_pick_the_lds_layout_by_size():
-    """Without a tune cache: two T-tables (64 KiB of LDS) up to 4 MiB, where
-    the table fill is a large part of a launch, four from 8 MiB on; 64
-    copies always mean two tables."""
+    """Without a tune cache: two T-tables (64 KiB of LDS) at every size, one
+    workgroup per CU up to 4 MiB and up to four per CU (two resident) from
+    8 MiB; explicit fields override; 64 copies always mean two tables."""
     import os
     A = lib()
     here = os.path.dirname(os.path.abspath(A.lib._name))
@@ -194,9 +194,12 @@ def test_default_shapes_pick_the_lds_layout_by_size():
     s = shape(128, int(4 * MiB * scale))
     assert (s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (2, 512, 2), s
     s = shape(128, int(8 * MiB * scale))
-    assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 4, 1024, 2), s
+    assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 2), s
+    assert s["grid"] == 2 * cus, s          # four per CU, clamped to the 2 chunks per CU there are
+    s = shape(128, int(32 * MiB * scale))
+    assert (s["wg_size"], s["blocks_per_lane"], s["grid"]) == (512, 4, 4 * cus), s
     assert shape(128, MiB, lds_copies=64)["lds_tables"] == 2
     assert shape(128, MiB, lds_tables=4)["lds_tables"] == 4
-    assert shape(128, 8 * MiB, lds_tables=2)["lds_tables"] == 2
+    assert shape(128, 8 * MiB, lds_tables=4)["lds_tables"] == 4
     s = shape(128, MiB, variant=2)
     assert (s["lds_copies"], s["lds_tables"]) == (0, 0), s
