@@ -35,7 +35,7 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchLayout> &tt, const C
                                          uint64_t b1, uint32_t lane)
 {
     const uint64_t nfull = a.len >> 4;
-    uint32_t krot[1];   // unused by the 32-copy table
+    uint32_t krot[1];   // unused by the four-table layout
     for (uint64_t s0 = b0; s0 < b1; s0 += 64 * BPL) {
         uint32_t ctr[BPL], ks[BPL][4];
         u32x4 d[BPL];

@@ -21,8 +21,9 @@
 //                into one rotate per column.
 //   kLayout2x32: 32 copies of T0 and of T2, interleaved in [0, 64 KiB) (T2 at
 //                +128 B), with the same fold: half the table fill of the other
-//                two for about 15% more VALU work per block, which pays for
-//                launches short enough that the fill is a large part of them.
+//                two for about 15% more VALU work per block, and two
+//                workgroups fit in a CU's LDS, so one's fill and barriers
+//                overlap the other's rounds.
 #pragma once
 
 #include "aes_tables.h"
