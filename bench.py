@@ -37,7 +37,8 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=3000,
+                    help="timed launches (one graph replay; 3000 x 8 MiB is about 23 ms)")
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--size", type=int, default=8 * MiB, help="bytes per buffer")
     ap.add_argument("--bits", type=int, default=128, choices=(128, 256))
