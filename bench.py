@@ -243,6 +243,25 @@ def measured_traffic(bits, size, variant):
     return int(fields["traffic_bytes_per_launch"])
 
 
+# VALU lane operations per 16-byte block of the default T-table launch at
+# 8 MiB, table fill and per-wave setup included: rocprofv3 SQ_INSTS_VALU x 64
+# / blocks (two-table layout, 512-thread workgroups, two per CU).
+VALU_PER_BLOCK_8MIB = {128: 329.9, 256: 449.9}
+
+
+def valu_roofline(args, gbs, cus, clk):
+    """The T-table kernel's second ceiling at 8 MiB: VALU issue at the
+    measured lane operations per block (its LDS-issue ceiling is `roofline`)."""
+    if args.variant == 2 or args.size != 8 * MiB:
+        return {}
+    v = VALU_PER_BLOCK_8MIB[args.bits]
+    peak = cus * 64 * clk / v * 16 / 1e9
+    return {"valu_roofline": {"bound": "valu", "achieved": round(gbs, 3), "peak": round(peak, 1), "unit": "GB/s",
+                              "frac": round(gbs / peak, 4),
+                              "note": f"{v} VALU lane-ops per block (rocprofv3 SQ_INSTS_VALU, fill and setup "
+                                      f"included) at 64 lane-ops per clock per CU"}}
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -427,6 +446,7 @@ def main():
                      "note": alu_note},
         "hbm_roofline": {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4)},
+        **valu_roofline(args, gbs, cus, clk),
         "eager_gbs": round(eager_gbs, 3),
         "warm_gbs": round(warm_gbs, 3),
         "single_launch_latency_us": round(lat, 2),
