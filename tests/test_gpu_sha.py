@@ -106,3 +106,31 @@ def test_benchmark_workload_sampled():
     d = dig.view(n, 32).cpu().numpy()
     for k, i in enumerate(idx):
         assert d[i].tobytes() == sha.sha256(host[k].tobytes()), int(i)
+
+
+@pytest.mark.parametrize("busy", [False, True], ids=["idle-stream", "busy-stream"])
+def test_records_in_place_and_uploaded(busy):
+    """A launch on an idle stream reads its records from pinned staging over
+    PCIe; on a busy stream (here behind a 256 MiB AES launch) they are
+    uploaded on a side stream first.  Two calls in a row, so the second
+    reuses the staging the first filled."""
+    torch = torch_cuda()
+    A = lib()
+    g = np.random.default_rng(21 if busy else 22)
+    n = 3000
+    msgs = [g.bytes(int(k)) for k in g.integers(0, 3000, size=n)]
+    offs = np.cumsum([0] + [len(m) for m in msgs])
+    buf = torch.from_numpy(np.frombuffer(b"".join(msgs) or b"\0", dtype=np.uint8).copy()).cuda()
+    big = torch.zeros(256 << 20, dtype=torch.uint8, device="cuda")
+    s = A.aes_expand_key(bytes(16))
+    for rep in range(2):
+        dig = torch.zeros(32 * n, dtype=torch.uint8, device="cuda")
+        items = [(buf.data_ptr() + int(offs[i]), len(m), dig.data_ptr() + 32 * i) for i, m in enumerate(msgs)]
+        torch.cuda.synchronize()
+        if busy:
+            A.aes_ctr_crypt(s, bytes(12), 1, big, big)      # keeps the stream busy for ~0.2 ms
+        A.sha256_batch(items)
+        torch.cuda.synchronize()
+        h = dig.cpu().numpy()
+        for i in range(n):
+            assert h[32 * i:32 * i + 32].tobytes() == sha.sha256(msgs[i]), (rep, i)
