@@ -219,7 +219,8 @@ typedef struct aes_engine aes_engine_t;
 typedef struct {
     uint64_t budget_bytes;      /* device bytes in flight (0 = 4 GiB)          */
     int32_t n_streams;          /* concurrent batch launches (0 = 2)           */
-    int32_t max_batch_reqs;     /* requests per launch (0 = 4096)              */
+    int32_t max_batch_reqs;     /* requests per batch (0 = 4096; a larger
+                                   batch is cut into launches of 4096)         */
     uint64_t max_batch_bytes;   /* payload bytes per launch (0 = 256 MiB or the
                                    budget if smaller; a larger request runs
                                    alone)                                      */
@@ -242,8 +243,9 @@ typedef struct {
     double busy_s;                  /* wall time with at least one launch in flight */
 } aes_stats_t;
 
-/* Create an engine (cfg may be NULL = defaults).  Starts its scheduler and
- * poller threads.  Errors: AES_EINVAL, AES_ENOMEM, AES_EDEVICE. */
+/* Create an engine (cfg may be NULL = defaults).  Starts its driver thread,
+ * which forms and launches batches and polls their completion events.
+ * Errors: AES_EINVAL, AES_ENOMEM, AES_EDEVICE. */
 int aes_engine_create(const aes_engine_cfg_t *cfg, aes_engine_t **out);
 
 /* Stop accepting work, finish everything submitted, release resources.
