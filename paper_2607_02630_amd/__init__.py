@@ -81,6 +81,10 @@ def _nonce(nonce: bytes) -> bytes:
 
 def launch_cfg(variant: int = 0, blocks_per_lane: int = 0, wg_size: int = 0, grid: int = 0,
                lds_copies: int = 0, lds_tables: int = 0) -> aes_launch_cfg_t:
+    """Launch shape for aes_ctr_crypt (aes_launch_cfg_t); zero fields keep the
+    default.  variant: AES_VARIANT_TTABLE (1) or AES_VARIANT_BITSLICE (2);
+    lds_copies / lds_tables: the T-table layout in LDS, 32 or 64 copies of 4
+    or 2 tables (64 copies only with 2 tables)."""
     c = aes_launch_cfg_t()
     c.variant, c.blocks_per_lane, c.wg_size, c.grid, c.lds_copies, c.lds_tables = (
         variant, blocks_per_lane, wg_size, grid, lds_copies, lds_tables)
@@ -205,6 +209,9 @@ def aes_ctr_crypt_batch(reqs, stream=None, cfg: aes_batch_cfg_t | None = None, d
 
 def batch_cfg(tile_bytes: int = 0, wg_size: int = 0, grid: int = 0, blocks_per_lane: int = 0,
               use_graph: int = 1) -> aes_batch_cfg_t:
+    """Launch shape for aes_ctr_crypt_batch (aes_batch_cfg_t); zero fields keep
+    the default (tiles sized to the batch, one 1024-thread workgroup per CU,
+    two blocks per lane, the captured graph)."""
     c = aes_batch_cfg_t()
     c.tile_bytes, c.wg_size, c.grid, c.blocks_per_lane, c.use_graph = (
         tile_bytes, wg_size, grid, blocks_per_lane, use_graph)
