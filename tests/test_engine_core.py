@@ -1,4 +1,5 @@
-"""Scheduling core of the serving engine, on the CPU under ThreadSanitizer.
+"""Scheduling core of the serving engine, on the CPU under ThreadSanitizer and
+AddressSanitizer.
 
 Builds tests/cpp/engine_core_test.cpp (host code only, no HIP, no cipher)
 and runs it: budget, FIFO admission, ticket lifecycle, timeouts, rejection
@@ -20,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
-@pytest.mark.parametrize("sanitize", ["thread", None])
+@pytest.mark.parametrize("sanitize", ["thread", "address", None])
 def test_engine_core(tmp_path, sanitize):
     exe = tmp_path / "engine_core_test"
     src = os.path.join(HERE, "cpp", "engine_core_test.cpp")

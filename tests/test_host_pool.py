@@ -1,5 +1,5 @@
 """Host thread pool of the library (validation and staging of large batches),
-on the CPU with and without ThreadSanitizer.
+on the CPU under ThreadSanitizer, AddressSanitizer and neither.
 
 Builds tests/cpp/host_pool_test.cpp together with the library's own
 csrc/host_pool.cpp (host code only, no HIP) and runs it: every index of a
@@ -19,7 +19,7 @@ POOL = os.path.join(HERE, "..", "paper_2607_02630_amd", "csrc", "host_pool.cpp")
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
-@pytest.mark.parametrize("sanitize", ["thread", None])
+@pytest.mark.parametrize("sanitize", ["thread", "address", None])
 def test_host_pool(tmp_path, sanitize):
     exe = tmp_path / "host_pool_test"
     src = os.path.join(HERE, "cpp", "host_pool_test.cpp")
