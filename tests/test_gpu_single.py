@@ -144,6 +144,21 @@ def test_counter_wrap(variant, ctr0, klen):
     assert np.array_equal(got, oracle.ctr(key, nonce, ctr0, data))
 
 
+@pytest.mark.parametrize("klen", [16, 32])
+@pytest.mark.parametrize("size", [(8 << 20) + 5, (64 << 20) + 21], ids=["8MiB+5", "64MiB+21"])
+def test_default_large_shapes_across_the_wrap(size, klen):
+    """The default shapes of large launches (two workgroups per CU in the
+    grid, two chunks per workgroup at 64 MiB), with the counter wrapping
+    mod 2^32 in the middle of the message and a ragged tail."""
+    g = np.random.default_rng(size & 0xFFFF)
+    key, nonce = g.bytes(klen), g.bytes(12)
+    data = W.payload(g, size)
+    ctr0 = (1 << 32) - (size // 16) // 2 - 3
+    log(f"AES-{8 * klen} {size} B default shape, ctr0 {ctr0:#x}")
+    got = gpu_crypt(key, nonce, ctr0, data)
+    assert np.array_equal(got, oracle.ctr(key, nonce, ctr0, data, threads=0))
+
+
 def test_decrypt_roundtrip_and_zero_length():
     torch = torch_cuda()
     L = lib()
