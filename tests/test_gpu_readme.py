@@ -21,9 +21,9 @@ def test_readme_usage_example():
     scope: dict = {}
     exec(compile(code, "README.md", "exec"), scope)
     torch.cuda.synchronize()
-    A, s, x, y = scope["A"], scope["s"], scope["x"], scope["y"]
-    # The engine request re-encrypted x into y with counter 7; decrypting y
-    # with the same key, nonce and counter gives x back.
-    back = A.aes_ctr_crypt(s, bytes(12), 7, y)
-    torch.cuda.synchronize()
-    assert torch.equal(back, x)
+    A, s, x, y, z = scope["A"], scope["s"], scope["x"], scope["y"], scope["z"]
+    # y = x under counter 1 (single call), z = x under counter 7 (engine):
+    # decrypting each with its own counter gives x back, and they differ.
+    assert torch.equal(A.aes_ctr_crypt(s, bytes(12), 1, y), x)
+    assert torch.equal(A.aes_ctr_crypt(s, bytes(12), 7, z), x)
+    assert not torch.equal(y, z)
