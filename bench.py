@@ -770,6 +770,7 @@ def serve_leg(torch, A, W, n_req=100_000, budget=4 << 30):
     log(f"serving leg: pool of {npool} requests, {total / 2**30:.2f} GiB")
     src = W.device_payload(total, 555)
     dst = torch.zeros_like(src)
+    torch.cuda.synchronize()        # the engine's streams are not ordered after torch's
     scheds = [A.aes_expand_key(g.bytes(16)) for _ in range(npool)]
     objs = [A.Request(s, g.bytes(12), int(g.integers(0, 1 << 32)), src.data_ptr() + int(o),
                       dst.data_ptr() + int(o), int(L)) for s, o, L in zip(scheds, offs, lens)]

@@ -257,6 +257,10 @@ int aes_engine_destroy(aes_engine_t *e);
  * Cipher and hash requests (flags = AES_FLAG_SHA256) may be mixed; a launch
  * runs the batch kernel for the cipher requests and the hash kernel for the
  * hash requests back to back on its stream.
+ * The engine launches on streams of its own, not ordered after any stream
+ * of the caller: the input must hold its final contents when aes_submit is
+ * called, and neither buffer may be touched again until the ticket
+ * completes.
  * Takes no lock; when 32768 requests are already queued (admitted requests
  * do not count) the call yields until the engine takes some.  Thread-safe;
  * calls racing with aes_engine_destroy are not allowed.

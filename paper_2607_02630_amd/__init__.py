@@ -219,7 +219,11 @@ def batch_cfg(tile_bytes: int = 0, wg_size: int = 0, grid: int = 0, blocks_per_l
 
 
 class Engine:
-    """submit -> poll/wait executor (aes_engine_*)."""
+    """submit -> poll/wait executor (aes_engine_*).
+
+    Its launches run on streams of its own: work that torch queued on its
+    stream for a request's buffers must have finished (torch.cuda.synchronize
+    or an event) before the request is submitted."""
 
     def __init__(self, budget_bytes: int = 0, n_streams: int = 0, max_batch_reqs: int = 0,
                  max_batch_bytes: int = 0, key_slots: int = 0, host_buffers: bool = False,

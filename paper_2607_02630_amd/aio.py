@@ -73,6 +73,7 @@ async def _serve(mode: str, size: int, clients: int, seconds: float, torch) -> f
     sched = aes_expand_key(bytes(range(16)))
     bufs = [(torch.randint(0, 256, (size,), dtype=torch.uint8, device="cuda"),
              torch.empty(size, dtype=torch.uint8, device="cuda")) for _ in range(clients)]
+    torch.cuda.synchronize()        # the engine's streams are not ordered after torch's
     header = os.urandom(4096)
     done = 0
     stop = time.perf_counter() + seconds

@@ -49,6 +49,7 @@ def make_requests(torch, n, seed, sizes=W.SERVING_SIZES, mix=W.SERVING_MIX, host
         reqs.append((key, nonce, ctr0, s, A.Request(s, nonce, ctr0, src.data_ptr() + pos, dst.data_ptr() + pos, L)))
         offs.append(pos)
         pos += L
+    torch.cuda.synchronize()        # the engine's streams are not ordered after torch's
     return src, dst, reqs, offs, lens
 
 
@@ -115,6 +116,7 @@ def test_oversize_and_ticket_semantics():
     torch = torch_cuda()
     A = lib()
     buf = torch.zeros(4 * MiB, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
     s = A.aes_expand_key(bytes(16))
     with A.Engine(budget_bytes=1 * MiB) as eng:
         with pytest.raises(A.AesError) as e:
@@ -179,6 +181,7 @@ def test_completion_fd_becomes_readable():
     torch = torch_cuda()
     A = lib()
     buf = torch.zeros(MiB, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
     s = A.aes_expand_key(bytes(32))
     with A.Engine() as eng:
         fd = eng.completion_fd()
@@ -207,6 +210,7 @@ def test_mixed_cipher_and_hash_requests():
     src = torch.from_numpy(src_h).cuda()
     dst = torch.zeros(total, dtype=torch.uint8, device="cuda")
     dig = torch.zeros(33 * n + 1, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
     reqs, meta, pos = [], [], 0
     for i in range(n):
         pos += int(g.integers(0, 16))                  # unaligned starts
