@@ -38,6 +38,7 @@ struct Shape {
     int grid;           // workgroups
     int copies;         // T-table replication (32 or 64 copies per table)
     int tables;         // T-tables in LDS: 4 (T0..T3) or 2 (T0, T2)
+    bool wave_groups;   // each wave computes its first chunk's group constants
 };
 
 // Arguments of the single-buffer kernels (passed by value in the kernarg

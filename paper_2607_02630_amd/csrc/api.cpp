@@ -229,6 +229,12 @@ Shape resolve_shape(int variant, int key_bits, uint64_t len, const aes_launch_cf
             sh.tables = 4;
     }
     clamp_grid(&sh, len);
+    // Per-wave first-chunk group constants pay off when two workgroups with
+    // the 64 KiB image share each CU (8 MiB AES-128: 7.64-7.69 against
+    // 7.74-7.78 us); with one workgroup per CU they cost more than wave 0
+    // computing them for all (4 MiB: 5.39 against 5.30 us).
+    sh.wave_groups = sh.variant == AES_VARIANT_TTABLE && sh.copies == 32 && sh.tables == 2 && sh.bpl == 2 &&
+                     sh.wg <= 512 && sh.grid >= 2 * di.num_cus;
     return sh;
 }
 

@@ -84,9 +84,10 @@ __device__ __forceinline__ uint32_t first_ctr(const CtrArgs &a, uint64_t start, 
     return a.ctr0 + static_cast<uint32_t>(start + 64u * wave * BPL);
 }
 
-template <int NR, int LAYOUT, int BPL, int WG, bool ALIGNED>
+template <int NR, int LAYOUT, int BPL, int WG, bool ALIGNED, bool WAVEG>
 __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
 {
+    static_assert(!WAVEG || BPL == 2, "per-wave group constants are built for two blocks per lane");
     __shared__ uint32_t lds[layout_lds_words(LAYOUT)];
 
     const uint64_t nfull = a.len >> 4;
@@ -115,33 +116,38 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     const uint32_t k = LAYOUT == kLayout2x64 ? lane : (lane & 31);
     TTable<LAYOUT> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
 
-    // Group constants of the first chunk: wave 0 computes every group the
-    // workgroup's chunk touches (one lane each, from the LDS tables) and the
+    // Group constants of the first chunk, from the LDS tables.  Either each
+    // wave computes its own (WAVEG: four lanes per group), or wave 0 computes
+    // every group the workgroup's chunk touches (one lane each) and the
     // waves pick theirs up after a second barrier.  Later chunks compute
-    // their own on the scalar unit while other waves keep the pipes busy.
-    static_assert(WG * BPL <= 4096, "a chunk must span at most kChunkGroups groups");
-    __shared__ u32x4 s_groups[kChunkGroups];
-    const uint32_t chunk_first = a.ctr0 + static_cast<uint32_t>(start);
-    const uint32_t g0 = chunk_first >> 8;
-    if (wave == 0) {
-        const uint32_t ng = ((chunk_first & 255u) + WG * BPL + 255u) >> 8;
-        if (lane < ng) {
-            uint32_t G[4];
-            group_consts_lds(tt, a, (g0 + lane) & 0xffffffu, G);
-            s_groups[lane] = u32x4{G[0], G[1], G[2], G[3]};
-        }
-    }
-    __syncthreads();
+    // theirs on the scalar unit while other waves keep the pipes busy.
     WaveGroups w;
-    {
-        const uint32_t first = first_ctr<BPL>(a, start, wave);
-        w.gA = first >> 8;
-        const u32x4 ga = s_groups[(w.gA - g0) & 0xffffffu];
-        const u32x4 gb = s_groups[(((first + 64u * BPL - 1u) >> 8) - g0) & 0xffffffu];
+    if constexpr (WAVEG) {
+        w = wave_groups_lds<LAYOUT, BPL>(tt, a, first_ctr<BPL>(a, start, wave), lane);
+    } else {
+        static_assert(WG * BPL <= 4096, "a chunk must span at most kChunkGroups groups");
+        __shared__ u32x4 s_groups[kChunkGroups];
+        const uint32_t chunk_first = a.ctr0 + static_cast<uint32_t>(start);
+        const uint32_t g0 = chunk_first >> 8;
+        if (wave == 0) {
+            const uint32_t ng = ((chunk_first & 255u) + WG * BPL + 255u) >> 8;
+            if (lane < ng) {
+                uint32_t G[4];
+                group_consts_lds(tt, a, (g0 + lane) & 0xffffffu, G);
+                s_groups[lane] = u32x4{G[0], G[1], G[2], G[3]};
+            }
+        }
+        __syncthreads();
+        {
+            const uint32_t first = first_ctr<BPL>(a, start, wave);
+            w.gA = first >> 8;
+            const u32x4 ga = s_groups[(w.gA - g0) & 0xffffffu];
+            const u32x4 gb = s_groups[(((first + 64u * BPL - 1u) >> 8) - g0) & 0xffffffu];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            w.GA[c] = ga[c];
-            w.GB[c] = gb[c];
+            for (int c = 0; c < 4; ++c) {
+                w.GA[c] = ga[c];
+                w.GB[c] = gb[c];
+            }
         }
     }
 
@@ -186,16 +192,28 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     }
 }
 
-template <int NR, int LAYOUT, int BPL, int WG>
-int launch_w(const CtrArgs &a, const Shape &sh, hipStream_t st)
+template <int NR, int LAYOUT, int BPL, int WG, bool WAVEG>
+int launch_g(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
     (void)hipGetLastError();   // not ours: left by earlier calls
     if (aligned)
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true, WAVEG>), dim3(sh.grid), dim3(WG), 0, st, a);
     else
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, false>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, false, WAVEG>), dim3(sh.grid), dim3(WG), 0, st, a);
     return launch_status();
+}
+
+// Per-wave group constants are built only where the shape rule uses them:
+// two tables x 32 copies, two blocks per lane, up to 512 threads.
+template <int NR, int LAYOUT, int BPL, int WG>
+int launch_w(const CtrArgs &a, const Shape &sh, hipStream_t st)
+{
+    if constexpr (LAYOUT == kLayout2x32 && BPL == 2 && WG <= 512) {
+        if (sh.wave_groups)
+            return launch_g<NR, LAYOUT, BPL, WG, true>(a, sh, st);
+    }
+    return launch_g<NR, LAYOUT, BPL, WG, false>(a, sh, st);
 }
 
 template <int NR, int LAYOUT, int BPL>

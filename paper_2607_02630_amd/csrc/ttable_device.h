@@ -169,6 +169,13 @@ struct TTable {
             return lds_at(lds, taddr<R>(v, REGION ? lb1 : lb0));
     }
 
+    // T0[byte of v at bit `pos`] for a lane-varying byte position (every
+    // layout keeps T0 entry x at 256*x + lb0).
+    __device__ __forceinline__ uint32_t t0_at(uint32_t v, uint32_t pos) const
+    {
+        return lds_at(lds, (__builtin_amdgcn_ubfe(v, pos, 8) << 8) | lb0);
+    }
+
     // One full round: s -> o with round key words k[0..3]; krot holds
     // rotr(k, 8) for the two-table fold.
     __device__ __forceinline__ void round(const uint32_t s[4], uint32_t o[4],
@@ -315,6 +322,42 @@ __device__ __forceinline__ WaveGroups wave_groups(const CtrArgs &a, uint32_t fir
     } else {
 #pragma unroll
         for (int c = 0; c < 4; ++c) w.GB[c] = w.GA[c];
+    }
+    return w;
+}
+
+// The same constants from the LDS tables, for a wave's first chunk, where
+// every wave of the CU starts at once (sixteen waves' scalar group constants
+// would queue on the CU's one scalar unit).  Four lanes per group: lane
+// 4h + c computes column c of the wave's first (h = 0) or second (h = 1)
+// group,
+//   G_c = rk2_c ^ T_t1[byte t1 of s1_1] ^ T_t2[byte t2 of s1_2] ^ T_t3[byte t3 of s1_3],
+// t_j = (j - c) mod 4 and T_t = rotl(T0, 8t), and v_readlane hands the eight
+// words to the whole wave.  Every lane of the wave must be active (lanes 8
+// and up compute values nobody reads).
+template <int LAYOUT, int N>
+__device__ __forceinline__ WaveGroups wave_groups_lds(const TTable<LAYOUT> &tt, const CtrArgs &a, uint32_t first,
+                                                      uint32_t lane)
+{
+    static_assert(64 * N <= 256, "a wave's counters must span at most two groups");
+    WaveGroups w;
+    w.gA = first >> 8;
+    const uint32_t g = (lane & 4) ? (first + 64u * N - 1u) >> 8 : w.gA;
+    const uint32_t c = lane & 3;
+    const uint32_t s1[3] = {a.k1[1] ^ tt.template get<2, 0>(g ^ (a.x0 >> 16)),
+                            a.k1[2] ^ tt.template get<1, 1>(g ^ a.x0),
+                            a.k1[3] ^ tt.template get<0, 2>(g ^ (a.x0 << 16))};
+    uint32_t G = 0;
+#pragma unroll
+    for (uint32_t j = 1; j <= 3; ++j) {
+        const uint32_t t = (j - c) & 3u;
+        const uint32_t e = tt.t0_at(s1[j - 1], 8u * t);
+        G ^= __builtin_amdgcn_alignbit(e, e, (32u - 8u * t) & 31u);   // rotl(e, 8t)
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w.GA[k] = a.rk[8 + k] ^ static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(G), k));
+        w.GB[k] = a.rk[8 + k] ^ static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(G), 4 + k));
     }
     return w;
 }

@@ -159,6 +159,29 @@ def test_default_large_shapes_across_the_wrap(size, klen):
     assert np.array_equal(got, oracle.ctr(key, nonce, ctr0, data, threads=0))
 
 
+@pytest.mark.parametrize("klen", [16, 32])
+@pytest.mark.parametrize("wg", [256, 512])
+@pytest.mark.parametrize("per_cu", [2, 4])
+def test_per_wave_group_constants(per_cu, wg, klen):
+    """Two-table shapes with two blocks per lane and at least two workgroups
+    per CU, where every wave computes its first chunk's group constants
+    itself: 8 MiB and a ragged tail, from a start counter inside a group,
+    wrapping mod 2^32 part-way."""
+    torch = torch_cuda()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    g = np.random.default_rng(11 * wg + klen + per_cu)
+    key, nonce = g.bytes(klen), g.bytes(12)
+    data = W.payload(g, (8 << 20) + 16 * 37 + 5)
+    ctr0 = 0xFFFFF0F7
+    cfg = lib().launch_cfg(variant=1, lds_copies=32, lds_tables=2, blocks_per_lane=2, wg_size=wg,
+                           grid=per_cu * cus)
+    shape = lib().launch_shape(8 * klen, len(data), cfg)
+    assert shape["grid"] >= 2 * cus, shape
+    log(f"per-wave group constants: AES-{8 * klen} wg {wg} grid {shape['grid']}")
+    got = gpu_crypt(key, nonce, ctr0, data, cfg=cfg)
+    assert np.array_equal(got, oracle.ctr(key, nonce, ctr0, data, threads=0))
+
+
 def test_decrypt_roundtrip_and_zero_length():
     torch = torch_cuda()
     L = lib()
