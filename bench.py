@@ -245,8 +245,9 @@ def measured_traffic(bits, size, variant):
 
 # VALU lane operations per 16-byte block of the default T-table launch at
 # 8 MiB, table fill and per-wave setup included: rocprofv3 SQ_INSTS_VALU x 64
-# / blocks (two-table layout, 512-thread workgroups, two per CU).
-VALU_PER_BLOCK_8MIB = {128: 329.9, 256: 449.9}
+# / blocks (two-table layout, 512-thread workgroups, two per CU, each wave
+# computing its first chunk's group constants).
+VALU_PER_BLOCK_8MIB = {128: 347.0, 256: 467.0}
 
 
 def valu_roofline(args, gbs, cus, clk):
