@@ -166,7 +166,8 @@ def test_per_wave_group_constants(per_cu, wg, klen):
     """Two-table shapes with two blocks per lane and at least two workgroups
     per CU, where every wave computes its first chunk's group constants
     itself: 8 MiB and a ragged tail, from a start counter inside a group,
-    wrapping mod 2^32 part-way."""
+    wrapping mod 2^32 part-way; with four workgroups per CU the buffers are
+    unaligned (the byte-wise load and store path)."""
     torch = torch_cuda()
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     g = np.random.default_rng(11 * wg + klen + per_cu)
@@ -177,8 +178,9 @@ def test_per_wave_group_constants(per_cu, wg, klen):
                            grid=per_cu * cus)
     shape = lib().launch_shape(8 * klen, len(data), cfg)
     assert shape["grid"] >= 2 * cus, shape
-    log(f"per-wave group constants: AES-{8 * klen} wg {wg} grid {shape['grid']}")
-    got = gpu_crypt(key, nonce, ctr0, data, cfg=cfg)
+    in_off, out_off = (3, 5) if per_cu == 4 else (0, 0)
+    log(f"per-wave group constants: AES-{8 * klen} wg {wg} grid {shape['grid']} offsets {in_off}/{out_off}")
+    got = gpu_crypt(key, nonce, ctr0, data, cfg=cfg, in_off=in_off, out_off=out_off)
     assert np.array_equal(got, oracle.ctr(key, nonce, ctr0, data, threads=0))
 
 
