@@ -115,7 +115,12 @@ typedef enum {
  *   lds_tables       T-tables held in LDS, T-table only: 4 (T0..T3, 32 copies,
  *                    128 KiB) or 2 (T0 and T2, T1 and T3 by rotation: 32
  *                    copies in 64 KiB, or 64 copies in 128 KiB).  64 copies
- *                    imply 2 tables; 64 copies of 4 tables is AES_EINVAL. */
+ *                    imply 2 tables; 64 copies of 4 tables is AES_EINVAL.
+ *   wave_groups      set by aes_ctr_launch_shape, ignored on input: 1 when
+ *                    every wave computes the counter-group constants of its
+ *                    first chunk itself (2 tables of 32 copies, 2 blocks per
+ *                    lane, <= 512 threads and at least two workgroups per
+ *                    CU), 0 when wave 0 computes them for its workgroup. */
 typedef struct {
     int32_t variant;
     int32_t blocks_per_lane;
@@ -123,7 +128,8 @@ typedef struct {
     int32_t grid;
     int32_t lds_copies;
     int32_t lds_tables;
-    int32_t reserved[2];
+    int32_t wave_groups;
+    int32_t reserved;
 } aes_launch_cfg_t;
 
 /* aes_ctr_crypt with an explicit launch shape (cfg may be NULL = defaults).

@@ -163,7 +163,8 @@ def launch_shape(key_bits: int, length: int, cfg: aes_launch_cfg_t | None = None
     _check(lib.aes_ctr_launch_shape(key_bits, length, ctypes.byref(cfg) if cfg is not None else None,
                                     ctypes.byref(out)), "aes_ctr_launch_shape")
     return {"variant": out.variant, "blocks_per_lane": out.blocks_per_lane, "wg_size": out.wg_size,
-            "grid": out.grid, "lds_copies": out.lds_copies, "lds_tables": out.lds_tables}
+            "grid": out.grid, "lds_copies": out.lds_copies, "lds_tables": out.lds_tables,
+            "wave_groups": out.wave_groups}
 
 
 def make_sha_desc_array(items) -> ctypes.Array:

@@ -38,7 +38,7 @@ class aes_launch_cfg_t(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("blocks_per_lane", ctypes.c_int32),
                 ("wg_size", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("lds_copies", ctypes.c_int32), ("lds_tables", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("wave_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class aes_ctr_desc_t(ctypes.Structure):

@@ -259,6 +259,7 @@ extern "C" int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_c
     out->grid = sh.grid;
     out->lds_copies = sh.copies;
     out->lds_tables = sh.tables;
+    out->wave_groups = sh.wave_groups ? 1 : 0;
     return AES_OK;
 }
 

@@ -177,7 +177,7 @@ def test_per_wave_group_constants(per_cu, wg, klen):
     cfg = lib().launch_cfg(variant=1, lds_copies=32, lds_tables=2, blocks_per_lane=2, wg_size=wg,
                            grid=per_cu * cus)
     shape = lib().launch_shape(8 * klen, len(data), cfg)
-    assert shape["grid"] >= 2 * cus, shape
+    assert shape["grid"] >= 2 * cus and shape["wave_groups"] == 1, shape
     in_off, out_off = (3, 5) if per_cu == 4 else (0, 0)
     log(f"per-wave group constants: AES-{8 * klen} wg {wg} grid {shape['grid']} offsets {in_off}/{out_off}")
     got = gpu_crypt(key, nonce, ctr0, data, cfg=cfg, in_off=in_off, out_off=out_off)
@@ -236,6 +236,10 @@ def test_default_shapes_pick_the_lds_layout_by_size():
     s = shape(128, int(8 * MiB * scale))
     assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 2), s
     assert s["grid"] == 2 * cus, s          # four per CU, clamped to the 2 chunks per CU there are
+    assert s["wave_groups"] == 1, s         # two workgroups per CU: each wave its own group constants
+    assert shape(128, int(4 * MiB * scale))["wave_groups"] == 0
+    assert shape(128, int(8 * MiB * scale), wg_size=1024)["wave_groups"] == 0
+    assert shape(128, int(8 * MiB * scale), lds_tables=4)["wave_groups"] == 0
     s = shape(128, int(32 * MiB * scale))
     assert (s["wg_size"], s["blocks_per_lane"], s["grid"]) == (512, 4, 4 * cus), s
     assert shape(128, MiB, lds_copies=64)["lds_tables"] == 2
