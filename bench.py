@@ -3,11 +3,13 @@
 
 Workload (the headline): AES-128-CTR over 8 MiB buffers of uniform random
 bytes, seeded key and nonce, counter from 1, inputs resident in HBM.  One
-step = one aes_ctr_crypt of one 8 MiB buffer (keystream + XOR, one kernel
-launch).  Buffers rotate over more than 512 MiB so the 256 MB Infinity Cache
-cannot serve repeats.  The K timed steps are replayed from a captured HIP
-graph so that Python launch overhead does not cap the kernel rate; the eager
-(one ctypes call per step) rate is reported beside it.
+launch = one aes_ctr_crypt of one 8 MiB buffer (keystream + XOR, one kernel
+launch).  One step = one replay of a captured HIP graph of K such launches
+(K sized so a replay lasts at least 20 ms, recorded in
+config.launches_per_step), so the replay's own fixed cost is spread over K
+launches and the per-launch rate does not depend on --steps.  Buffers rotate
+over more than 512 MiB so the 256 MB Infinity Cache cannot serve repeats.
+The eager (one ctypes call per launch) rate is reported beside it.
 
 Prints ONE JSON line.  Extra legs (--sweep, --batch, --serve) add fields to
 that line; the CPU oracle leg (cpu_baseline) runs unless --no-cpu.
@@ -37,9 +39,11 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3000,
-                    help="timed launches (one graph replay; 3000 x 8 MiB is about 23 ms)")
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps; a step is one replay of a captured graph of K launches")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before the timed ones")
+    ap.add_argument("--launches", type=int, default=0,
+                    help="launches per step, K (0 = enough for a replay of at least 20 ms)")
     ap.add_argument("--size", type=int, default=8 * MiB, help="bytes per buffer")
     ap.add_argument("--bits", type=int, default=128, choices=(128, 256))
     ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 T-table, 2 bitsliced")
@@ -107,6 +111,43 @@ def steady_state(torch, A, sched, nonce, ins, outs, steps, warmup, cfg=None, rep
         runs.append(t)
     runs.sort(key=lambda r: r.ms)
     return runs[len(runs) // 2], g
+
+
+MIN_STEP_S = 0.020     # a timed step (one graph replay) lasts at least this long
+
+
+def launches_for(torch, A, sched, nonce, ins, outs, cfg=None, min_s=MIN_STEP_S):
+    """K, the launches per step: a graph of 100 launches is replayed three
+    times and K is the smallest multiple of the buffer count whose replay
+    lasts at least min_s at that rate."""
+    n = len(ins)
+    t, g = steady_state(torch, A, sched, nonce, ins, outs, 100, 0, cfg, repeats=3)
+    del g
+    per_launch_s = t.ms * 1e-3 / 100
+    k = math.ceil(min_s / per_launch_s)
+    return max(n, math.ceil(k / n) * n)
+
+
+def replayed_steps(torch, A, sched, nonce, ins, outs, launches, steps, warmup, cfg=None):
+    """The timed region: `steps` replays of one captured graph of `launches`
+    back-to-back aes_ctr_crypt calls over the rotating buffers, after
+    `warmup` untimed replays.  HIP events on the replay stream bracket the
+    timed replays, with a device synchronisation on both sides.  Returns the
+    Timer (ms = all timed steps)."""
+    n = len(ins)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for i in range(launches):
+            A.aes_ctr_crypt(sched, nonce, 1, ins[i % n], outs[i % n], cfg=cfg)
+    for _ in range(max(warmup, 1)):
+        g.replay()
+    torch.cuda.synchronize()
+    with Timer(torch) as t:
+        for _ in range(steps):
+            g.replay()
+    del g
+    return t
 
 
 def eager(torch, A, sched, nonce, ins, outs, steps, cfg=None):
@@ -377,12 +418,15 @@ def main():
         sys.exit(3)
     log(f"parity vs oracle digest: {parity}; {len(ins)} buffer pairs")
 
-    t, _g = steady_state(torch, A, sched, nonce, ins, outs, args.steps, args.warmup, cfg)
+    K = args.launches or launches_for(torch, A, sched, nonce, ins, outs, cfg)
+    t = replayed_steps(torch, A, sched, nonce, ins, outs, K, args.steps, args.warmup, cfg)
     ms_per_step = t.ms / args.steps
-    gbs = args.size / (ms_per_step * 1e-3) / 1e9
-    log(f"steady state: {ms_per_step * 1e3:.2f} us/step, {gbs:.1f} GB/s (wall {t.wall_ms:.1f} ms)")
-    te = eager(torch, A, sched, nonce, ins, outs, min(args.steps, 2000), cfg)
-    eager_gbs = args.size * min(args.steps, 2000) / (te.ms * 1e-3) / 1e9
+    us_per_launch = t.ms * 1e3 / (args.steps * K)
+    gbs = args.size / (us_per_launch * 1e-6) / 1e9
+    log(f"steady state: {args.steps} steps of {K} launches, {ms_per_step:.2f} ms/step, "
+        f"{us_per_launch:.3f} us/launch, {gbs:.1f} GB/s (wall {t.wall_ms:.1f} ms)")
+    te = eager(torch, A, sched, nonce, ins, outs, 2000, cfg)
+    eager_gbs = args.size * 2000 / (te.ms * 1e-3) / 1e9
     lat = single_latency_us(torch, A, sched, nonce, ins[0], outs[0], cfg=cfg)
     e2e, e2e_out = end_to_end_gbs(torch, A, sched, nonce, payload)
     pipe = {f"{c // 1024} KiB": round(end_to_end_pipelined_gbs(torch, A, sched, nonce, payload, e2e_out, chunk=c), 3)
@@ -395,33 +439,34 @@ def main():
 
     # Warm: the same buffer pair every launch (in + out stay in the 256 MB
     # Infinity Cache); reported beside the cold figure, never as `value`.
-    tw, _gw = steady_state(torch, A, sched, nonce, ins[:1], outs[:1], args.steps, 20, cfg)
-    warm_gbs = args.size / (tw.ms / args.steps * 1e-3) / 1e9
-    del _gw
+    tw = replayed_steps(torch, A, sched, nonce, ins[:1], outs[:1], K, 3, 1, cfg)
+    warm_gbs = args.size * 3 * K / (tw.ms * 1e-3) / 1e9
 
     # Roofline of the dominant kernel: algorithmic bytes per launch = 2 x size
     # (payload in + out); average launch duration from the events above.
-    hbm_achieved = 2 * args.size / (ms_per_step * 1e-3) / 1e9
+    hbm_achieved = 2 * args.size / (us_per_launch * 1e-6) / 1e9
     nr = 10 if args.bits == 128 else 14
     # Roofline of the cipher kernel.  T-table kernel: bound by LDS issue;
     # gfx950 reads 128 B/clk per CU from LDS (32 banks x 4 B), i.e. 32 random
-    # 4-byte lookups per clock.  The method needs 16*Nr lookups per 16-byte
-    # block; with counter-mode caching of rounds 1-2 this kernel does 27
-    # fewer (133 for AES-128, 197 for AES-256), and the peak is taken at the
-    # kernel's own count.  Bitsliced kernel: bound by VALU issue (64 lane-ops
-    # per clock per CU, about 814 per AES-128 block).
+    # 4-byte lookups per clock.  The unit of work is the method's: 16*Nr table
+    # lookups per 16-byte block (160 for AES-128, 224 for AES-256), so the
+    # peak is 256 CUs x 2.4 GHz x 32 / (16*Nr) blocks per second.  With
+    # counter-mode caching of rounds 1-2 this kernel does 27 fewer (133 /
+    # 197); the ceiling at that count is in the note.  The bitsliced kernel
+    # has no lookups and is bound by VALU issue (64 lane-ops per clock per CU,
+    # at its own instruction count per block).
     clk = 2.4e9
     if args.variant == 2:
         valu_per_block = 814 if nr == 10 else 814 * 14 // 10
         alu_peak_gbs = cus * 64 * clk / valu_per_block * 16 / 1e9
         alu_note = f"payload GB/s vs the VALU-issue ceiling of {valu_per_block} ops per block"
-        method_peak = None
     else:
         lookups = 16 * nr - 27
-        alu_peak_gbs = cus * clk * 32 / lookups * 16 / 1e9
-        method_peak = cus * clk * 32 / (16 * nr) * 16 / 1e9
-        alu_note = (f"payload GB/s vs the LDS-issue ceiling at the kernel's {lookups} table lookups "
-                    f"per block (16*Nr = {16 * nr} without counter-mode caching: {method_peak:.1f} GB/s)")
+        alu_peak_gbs = cus * clk * 32 / (16 * nr) * 16 / 1e9
+        cached_peak = cus * clk * 32 / lookups * 16 / 1e9
+        alu_note = (f"payload GB/s vs the LDS-issue ceiling at the method's 16*Nr = {16 * nr} table lookups "
+                    f"per block; at the kernel's own {lookups} (counter-mode caching of rounds 1-2) the "
+                    f"ceiling is {cached_peak:.1f} GB/s")
     result = {
         "metric": "AES-CTR GB/s at 1/8 MiB; batched GB/s + p99 latency vs per-request launch",
         "value": round(gbs, 3),
@@ -429,7 +474,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 6),
+        "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -439,7 +484,9 @@ def main():
                                "kernel-only steady state, cold buffers (sweep 4 KiB-8 MiB + 256 MiB "
                                "in 'sweep')",
                    "key_bits": args.bits, "buffer_bytes": args.size, "buffers_rotated": len(ins),
-                   "timed_launch": "captured HIP graph of `steps` launches",
+                   "launches_per_step": K,
+                   "timed_launch": f"each step replays a captured HIP graph of {K} launches "
+                                   f"({us_per_launch:.3f} us each)",
                    "parity_vs_oracle_digest": parity},
         "roofline": {"bound": "alu", "achieved": round(gbs, 3), "peak": round(alu_peak_gbs, 1),
                      "unit": "GB/s", "frac": round(gbs / alu_peak_gbs, 4),
@@ -495,19 +542,21 @@ def one_mib_leg(torch, A, W, sched, nonce, args):
         gold = json.load(f)["sweep"][f"{args.bits}/{size}"]
     if digest != gold:
         raise SystemExit("1 MiB output differs from the oracle digest")
-    steps = 3000
-    t, _g = steady_state(torch, A, sched, nonce, ins, outs, steps, args.warmup)
-    us = t.ms / steps * 1e3
+    K = launches_for(torch, A, sched, nonce, ins, outs)
+    t = replayed_steps(torch, A, sched, nonce, ins, outs, K, args.steps, args.warmup)
+    us = t.ms * 1e3 / (args.steps * K)
     shape = A.launch_shape(args.bits, size)
-    out = {"gbps": round(size / (us * 1e-6) / 1e9, 3), "us_per_launch": round(us, 3), "steps": steps,
-           "buffers_rotated": len(ins), "parity_vs_oracle_digest": True, "shape": shape}
-    log(f"1 MiB: {us:.2f} us/step, {out['gbps']:.1f} GB/s")
-    del ins, outs, _g
+    out = {"gbps": round(size / (us * 1e-6) / 1e9, 3), "us_per_launch": round(us, 3), "steps": args.steps,
+           "launches_per_step": K, "buffers_rotated": len(ins), "parity_vs_oracle_digest": True, "shape": shape}
+    log(f"1 MiB: {args.steps} steps of {K} launches, {us:.3f} us/launch, {out['gbps']:.1f} GB/s")
+    del ins, outs
     torch.cuda.empty_cache()
     return out
 
 
 def run_sweep(torch, A, W, args):
+    with open(os.path.join(HERE, "tests", "golden", "ctr_digests.json")) as f:
+        gold = json.load(f)["sweep"]
     out = {}
     for bits in (128, 256):
         key, nonce = W.sweep_key(bits)
@@ -516,12 +565,18 @@ def run_sweep(torch, A, W, args):
             for variant in (1, 2):
                 cfg = A.launch_cfg(variant=variant)
                 payload, ins, outs = make_buffers(torch, W, size, bits)
+                # Parity gate on this exact (variant, key size, size) before it is timed.
+                A.aes_ctr_crypt(sched, nonce, 1, ins[0], outs[0], cfg=cfg)
+                torch.cuda.synchronize()
+                digest = hashlib.sha256(outs[0].cpu().numpy().tobytes()).hexdigest()
+                if digest != gold[f"{bits}/{size}"]:
+                    raise SystemExit(f"sweep: variant {variant} AES-{bits} {size} B differs from the oracle digest")
                 steps = max(20, min(2000, int(16e9 / size)))   # replays of >= ~10 ms, like the headline
                 t, _ = steady_state(torch, A, sched, nonce, ins, outs, steps, 10, cfg, repeats=3)
                 ms = t.ms / steps
                 lat = single_latency_us(torch, A, sched, nonce, ins[0], outs[0], reps=20, cfg=cfg)
                 row = {"kernel_gbs": round(size / (ms * 1e-3) / 1e9, 3), "us_per_launch": round(ms * 1e3, 3),
-                       "single_launch_us": round(lat, 2)}
+                       "single_launch_us": round(lat, 2), "parity_vs_oracle_digest": True}
                 if variant == 1:
                     row["end_to_end_pinned_gbs"] = round(end_to_end_gbs(torch, A, sched, nonce, payload)[0], 3)
                 out[f"aes{bits}/{'tt' if variant == 1 else 'bs'}/{size}"] = row

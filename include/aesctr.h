@@ -223,7 +223,10 @@ int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n,
 typedef struct aes_engine aes_engine_t;
 
 typedef struct {
-    uint64_t budget_bytes;      /* device bytes in flight (0 = 4 GiB)          */
+    uint64_t budget_bytes;      /* bytes in flight (0 = 4 GiB): the buffers of
+                                   every admitted request (input and output,
+                                   counted once when in place; a hash request's
+                                   message and digest) plus its descriptor     */
     int32_t n_streams;          /* concurrent batch launches (0 = 2)           */
     int32_t max_batch_reqs;     /* requests per batch (0 = 4096; a larger
                                    batch is cut into launches of 4096)         */
@@ -247,6 +250,12 @@ typedef struct {
     double mean_batch_reqs;
     double p50_us, p99_us, p999_us; /* arrival (submit) -> completion seen by the poller */
     double busy_s;                  /* wall time with at least one launch in flight */
+    double max_us;                  /* slowest request, same clock as p50_us */
+    uint64_t key_hits;              /* cipher requests whose key schedule was already
+                                       resident in a key slot (key_slots > 0) */
+    uint64_t key_misses;            /* ... that had to install it (evicting the least
+                                       recently used unreferenced slot) or, with
+                                       every slot referenced, carried it inline */
 } aes_stats_t;
 
 /* Create an engine (cfg may be NULL = defaults).  Starts its driver thread,

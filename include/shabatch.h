@@ -41,13 +41,15 @@ typedef struct {
  * call time: the caller may reuse it when the call returns.  Asynchronous on
  * `stream`; the descriptors travel through staging that the library keeps
  * per (device, stream) until the process ends: two pinned host buffers and
- * two device buffers of 4 MiB each, and a side stream for their uploads.
+ * two device buffers of 4 MiB each, and a side stream for their uploads (an
+ * engine's streams hand theirs to the next engine when it is destroyed).
  * Calls with more than 131,072 messages are cut into launches of that many;
  * the call returns once the last launch is queued, which may wait for the
  * launch two before it.  A message may be at most 2^61 - 1
  * bytes (the bit length must fit the 64-bit length field).
  * Errors: AES_EINVAL (null desc with n > 0, null digest, null in with
- * len > 0, reserved != 0), AES_ERANGE (message too long), AES_EOVERLAP
+ * len > 0, reserved != 0, a stream that is being captured -- a captured
+ * graph would keep reading staging that later calls rewrite), AES_ERANGE (message too long), AES_EOVERLAP
  * (digest overlaps its input), AES_ENOMEM, AES_EDEVICE.  Thread-safe for
  * calls on distinct streams; calls on one stream are serialised. */
 int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream);

@@ -63,6 +63,14 @@ def _nbytes(x) -> int:
     return x.numel() * x.element_size()
 
 
+def _check_room(x, n: int, what: str) -> None:
+    """A tensor argument must hold at least n bytes: the kernels read and
+    write exactly n bytes from its start, so a smaller tensor would be read or
+    written past its end."""
+    if _is_tensor(x) and _nbytes(x) < n:
+        raise ValueError(f"{what} holds {_nbytes(x)} bytes, fewer than the {n} bytes requested")
+
+
 def _stream(stream) -> int | None:
     if stream is None:
         import torch
@@ -103,6 +111,10 @@ def aes_ctr_crypt(sched: aes_sched_t, nonce: bytes, ctr0: int, x, out=None, leng
         import torch
         out = torch.empty_like(x)
     n = length if length is not None else _nbytes(x)
+    if n < 0:
+        raise ValueError("length must be >= 0")
+    _check_room(x, n, "x")
+    _check_room(out, n, "out")
     st = _stream(stream)
     if cfg is None:
         rc = lib.aes_ctr_crypt(ctypes.byref(sched), _nonce(nonce), ctr0 & 0xFFFFFFFF,
@@ -121,6 +133,10 @@ class Request:
         self.sched, self.nonce, self.ctr0 = sched, _nonce(nonce), ctr0 & 0xFFFFFFFF
         self.x, self.out = x, out
         self.length = length if length is not None else _nbytes(x)
+        if self.length < 0:
+            raise ValueError("length must be >= 0")
+        _check_room(x, self.length, "x")
+        _check_room(out, self.length, "out")
 
     def desc(self) -> aes_ctr_desc_t:
         d = aes_ctr_desc_t()
@@ -140,6 +156,10 @@ class HashRequest:
     def __init__(self, x, digest, length: int | None = None):
         self.x, self.digest = x, digest
         self.length = length if length is not None else _nbytes(x)
+        if self.length < 0:
+            raise ValueError("length must be >= 0")
+        _check_room(x, self.length, "x")
+        _check_room(digest, 32, "digest")
 
     def desc(self) -> aes_ctr_desc_t:
         d = aes_ctr_desc_t()
@@ -173,6 +193,8 @@ def make_sha_desc_array(items) -> ctypes.Array:
     items = list(items)
     arr = (N.sha256_desc_t * max(len(items), 1))()
     for i, (x, length, digest) in enumerate(items):
+        _check_room(x, int(length), f"message {i}")
+        _check_room(digest, 32, f"digest {i}")
         arr[i].in_ = _addr(x)
         arr[i].len = int(length)
         arr[i].digest = _addr(digest)

@@ -72,7 +72,8 @@ class aes_stats_t(ctypes.Structure):
                 ("queued_now", ctypes.c_uint64), ("inflight_now", ctypes.c_uint64),
                 ("mean_batch_reqs", ctypes.c_double), ("p50_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("p999_us", ctypes.c_double),
-                ("busy_s", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("key_hits", ctypes.c_uint64), ("key_misses", ctypes.c_uint64)]
 
 
 # Every exported name and its (restype, argtypes).

@@ -142,6 +142,15 @@ uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus);
 void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o);
 int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
                    int bpl, bool use_graph, bool allow_small);
+// Completes a staged table (header + n records at buf): assigns each
+// record's first tile and fills the header.  Returns the table's bytes, or 0
+// if the tile count would overflow 31 bits.
+size_t finish_stage(uint8_t *buf, size_t n, uint32_t tile_blocks);
+
+// Returns the staging context of stream st on device to the device's free
+// list (the stream is about to be destroyed; its work must have finished or
+// be finishing).  A later stream reuses it instead of allocating another.
+void release_batch_stream(int device, hipStream_t st);
 
 // Defaults before tuning, per variant and size.
 Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &di);

@@ -56,8 +56,13 @@ struct BatchCtx {
 
 std::mutex g_ctx_mu;
 // Contexts live until process exit (freeing them from a static destructor
-// could run after the HIP runtime has shut down).
+// could run after the HIP runtime has shut down).  A stream's context goes
+// back to its device's free list when the stream is retired
+// (release_batch_stream, called by aes_engine_destroy before it destroys its
+// streams), and the next new stream on that device takes it over, so
+// creating and destroying engines does not grow memory.
 std::map<std::pair<int, void *>, BatchCtx *> g_ctx;
+std::map<int, std::vector<BatchCtx *>> g_free;
 
 int init_ctx(BatchCtx *c, int device)
 {
@@ -82,6 +87,14 @@ BatchCtx *get_ctx(int device, void *stream, int *rc)
     if (it != g_ctx.end()) {
         *rc = AES_OK;
         return it->second;
+    }
+    std::vector<BatchCtx *> &fl = g_free[device];
+    if (!fl.empty()) {
+        BatchCtx *c = fl.back();
+        fl.pop_back();
+        g_ctx[key] = c;
+        *rc = AES_OK;
+        return c;
     }
     BatchCtx *c = new BatchCtx();
     *rc = init_ctx(c, device);
@@ -140,6 +153,8 @@ int build_graph(BatchCtx *c, int s, int grid, int bpl)
     return AES_OK;
 }
 
+}  // namespace
+
 // Completes staging slot `buf` whose n records are written: assigns first
 // tiles and fills the header.  Returns the bytes to upload, or 0 if the tile
 // count would overflow.
@@ -162,6 +177,8 @@ size_t finish_stage(uint8_t *buf, size_t n, uint32_t tile_blocks)
     h->next = 0;
     return sizeof(BatchHeader) + n * sizeof(BatchDesc);
 }
+
+namespace {
 
 // Records per part of the host's parallel record building.
 constexpr size_t kRecordGrain = 256;
@@ -258,6 +275,31 @@ int launch_filled(int device, hipStream_t st, size_t n, int tile_bytes, int grid
 }
 
 }  // namespace
+
+void release_batch_stream(int device, hipStream_t st)
+{
+    BatchCtx *c = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        auto it = g_ctx.find(std::make_pair(device, static_cast<void *>(st)));
+        if (it == g_ctx.end())
+            return;
+        c = it->second;
+        g_ctx.erase(it);
+    }
+    {
+        // The stream's last launches read the staging slots: wait for them
+        // before another stream may refill a slot.
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (int i = 0; i < kSlots; ++i) {
+            if (c->used[i] && hipEventSynchronize(c->done[i]) != hipSuccess)
+                note_device_error(hipGetLastError());
+            c->used[i] = false;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    g_free[device].push_back(c);
+}
 
 uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus)
 {

@@ -307,8 +307,13 @@ extern "C" int aes_engine_destroy(aes_engine_t *e)
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(e->device);
-    for (hipStream_t st : e->streams)
+    // The driver has retired every launch; the streams' staging contexts go
+    // back to the device's pools for the next engine.
+    for (hipStream_t st : e->streams) {
+        aesctr::release_batch_stream(e->device, st);
+        aesctr::release_sha_stream(e->device, st);
         (void)hipStreamDestroy(st);
+    }
     for (hipEvent_t ev : e->events)
         (void)hipEventDestroy(ev);
     if (prev >= 0)
@@ -364,12 +369,14 @@ extern "C" int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t
             r.rec.in = din;
             r.rec.out = dout;
         }
-        r.bytes = d->len + 32;
+        r.bytes = d->len + 32 + sizeof(aesctr::ShaRecord);
         return e->core.submit(std::move(r), ticket, t_arrival_ns);
     }
     if ((rc = aesctr::check_desc(*d)) != AES_OK)
         return rc;
-    r.bytes = d->len;
+    // Admission weight: the request's buffers while it is in flight (input
+    // and output, once when in place) and its descriptor record.
+    r.bytes = (d->in == d->out ? 1 : 2) * d->len + sizeof(BatchDesc);
     aesctr::make_batch_record(*d, &r.rec);
     if (e->host_buffers && d->len > 0) {
         // The kernel reads and writes the pinned host buffers directly.

@@ -50,7 +50,7 @@ namespace aesctr {
 template <class Record>
 struct EngineReq {
     uint64_t ticket = 0;
-    uint64_t bytes = 0;        // admission weight: payload bytes
+    uint64_t bytes = 0;        // admission weight: bytes the request holds in flight
     int64_t t_submit_ns = 0;
     Record rec{};
 };
@@ -179,6 +179,7 @@ public:
             o->p50_us = pct(0.50);
             o->p99_us = pct(0.99);
             o->p999_us = pct(0.999);
+            o->max_us = v.back();
         }
     }
 

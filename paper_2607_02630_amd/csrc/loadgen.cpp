@@ -116,7 +116,7 @@ extern "C" int aes_load_engine(aes_engine_t *e, const aes_ctr_desc_t *pool, size
     out->p50_us = st.p50_us;
     out->p99_us = st.p99_us;
     out->p999_us = st.p999_us;
-    out->max_us = 0;
+    out->max_us = st.max_us;
     return first_err.load();
 }
 

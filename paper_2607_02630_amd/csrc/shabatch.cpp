@@ -44,8 +44,11 @@ struct ShaCtx {
 };
 
 std::mutex g_sha_mu;
-// Contexts live until process exit (see batch.cpp for why).
+// Contexts live until process exit (see batch.cpp for why); a retired
+// stream's context goes to its device's free list for the next stream
+// (release_sha_stream).  The coherent slots in particular are never freed.
 std::map<std::pair<int, void *>, ShaCtx *> g_sha;
+std::map<int, std::vector<ShaCtx *>> g_sha_free;
 
 ShaCtx *get_ctx(int device, void *stream, int *rc)
 {
@@ -54,6 +57,14 @@ ShaCtx *get_ctx(int device, void *stream, int *rc)
     if (it != g_sha.end()) {
         *rc = AES_OK;
         return it->second;
+    }
+    std::vector<ShaCtx *> &fl = g_sha_free[device];
+    if (!fl.empty()) {
+        ShaCtx *c = fl.back();
+        fl.pop_back();
+        g_sha[{device, stream}] = c;
+        *rc = AES_OK;
+        return c;
     }
     ShaCtx *c = new ShaCtx();
     const size_t bytes = sizeof(ShaRecord) * kMaxShaBatch;
@@ -93,6 +104,30 @@ ShaCtx *get_ctx(int device, void *stream, int *rc)
 }  // namespace aesctr
 
 namespace aesctr {
+
+void release_sha_stream(int device, hipStream_t st)
+{
+    ShaCtx *c = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_sha_mu);
+        auto it = g_sha.find({device, static_cast<void *>(st)});
+        if (it == g_sha.end())
+            return;
+        c = it->second;
+        g_sha.erase(it);
+    }
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (int i = 0; i < kShaSlots; ++i) {
+            if (c->used[i] && hipEventSynchronize(c->done[i]) != hipSuccess)
+                note_device_error(hipGetLastError());
+            c->used[i] = false;
+        }
+        c->next = 0;
+    }
+    std::lock_guard<std::mutex> lk(g_sha_mu);
+    g_sha_free[device].push_back(c);
+}
 
 int check_sha(const void *in, uint64_t len, const void *digest)
 {
@@ -238,6 +273,13 @@ extern "C" int sha256_batch(const sha256_desc_t *desc, size_t n, void *stream)
     if (rc != AES_OK)
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // The call cannot be captured into a caller's graph: the graph would
+    // keep reading staging slots that later calls rewrite.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess)
+        return device_error();
+    if (cs != hipStreamCaptureStatusNone)
+        return AES_EINVAL;
     auto rec = [&](size_t i) {
         return ShaRecord{reinterpret_cast<uint64_t>(desc[i].in), desc[i].len,
                          reinterpret_cast<uint64_t>(desc[i].digest), 0};

@@ -28,4 +28,8 @@ int check_sha(const void *in, uint64_t len, const void *digest);
 // context and launches the hash kernel (kMaxShaBatch per launch).
 int launch_sha_records(int device, hipStream_t st, const ShaRecord *recs, size_t n, int num_cus);
 
+// Returns stream st's staging context to the device's free list (as
+// release_batch_stream does for the cipher batch).
+void release_sha_stream(int device, hipStream_t st);
+
 }  // namespace aesctr

@@ -217,3 +217,31 @@ def test_batch_validation_of_a_large_batch_reports_the_first_error():
     arr[7_000].len = 4096
     arr[8_000].sched = ctypes.pointer(bad)        # EINVAL, before the flags one
     assert A.lib.aes_ctr_crypt_batch(arr, n, None) == N.AES_EINVAL
+
+
+def test_binding_refuses_undersized_tensors_before_any_launch():
+    """A tensor smaller than the bytes asked for is refused in Python, before
+    the library is called, so no kernel can read or write past it (CPU
+    tensors stand in for device ones: the check never reaches the device)."""
+    import torch
+    import paper_2607_02630_amd as A
+    s = A.aes_expand_key(bytes(16))
+    x64, x32 = torch.zeros(64, dtype=torch.uint8), torch.zeros(32, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="out holds 32 bytes"):
+        A.aes_ctr_crypt(s, bytes(12), 0, x64, out=x32)
+    with pytest.raises(ValueError, match="x holds 64 bytes"):
+        A.aes_ctr_crypt(s, bytes(12), 0, x64, out=torch.zeros(128, dtype=torch.uint8), length=100)
+    with pytest.raises(ValueError, match="length"):
+        A.aes_ctr_crypt(s, bytes(12), 0, x64, out=x64, length=-1)
+    with pytest.raises(ValueError, match="out holds 32 bytes"):
+        A.Request(s, bytes(12), 0, x64, x32)
+    with pytest.raises(ValueError, match="x holds 64 bytes"):
+        A.Request(s, bytes(12), 0, x64, 0x1000, length=65)
+    with pytest.raises(ValueError, match="digest holds 16 bytes"):
+        A.HashRequest(x64, torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="message 0 holds 64 bytes"):
+        A.make_sha_desc_array([(x64, 65, torch.zeros(32, dtype=torch.uint8))])
+    # Tensors that are large enough pass the check (raw addresses are the
+    # caller's responsibility).
+    A.Request(s, bytes(12), 0, x64, x64, length=64)
+    A.HashRequest(x64, torch.zeros(32, dtype=torch.uint8))

@@ -65,13 +65,18 @@ def test_single_1mib_matches_oracle():
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("variant", [0, 2], ids=["default", "bs"])
 @pytest.mark.parametrize("bits", [128, 256])
 @pytest.mark.parametrize("size", W.SWEEP_SIZES + [W.BIG_SIZE])
-def test_sweep_full_size_digest(bits, size):
+def test_sweep_full_size_digest(bits, size, variant):
+    """Every sweep size, in the default launch shape and in the bitsliced
+    kernel's, against the oracle-written digest (the configurations the
+    benchmark's sweep times)."""
     key, nonce = W.sweep_key(bits)
     data = W.sweep_payload(size, bits)
-    log(f"sweep AES-{bits} {size} B")
-    got = gpu_crypt(key, nonce, 1, data)
+    log(f"sweep AES-{bits} {size} B variant {variant}")
+    cfg = lib().launch_cfg(variant=variant) if variant else None
+    got = gpu_crypt(key, nonce, 1, data, cfg=cfg)
     assert sha256(got) == golden()["sweep"][f"{bits}/{size}"]
 
 
