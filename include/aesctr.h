@@ -99,17 +99,21 @@ int aes_expand_key(const uint8_t *key, int key_bits, aes_sched_t *out);
 int aes_ctr_crypt(const aes_sched_t *sched, const uint8_t nonce[12], uint32_t ctr0,
                   const void *in, void *out, size_t len, void *stream);
 
-/* Kernel variants of the keystream (both give identical output). */
+/* Kernel variants of the keystream (all give identical output). */
 typedef enum {
     AES_VARIANT_AUTO = 0,      /* tuned choice */
     AES_VARIANT_TTABLE = 1,    /* round T-tables in LDS, replicated per bank */
-    AES_VARIANT_BITSLICE = 2   /* bitsliced: 32 blocks per 32-bit word */
+    AES_VARIANT_BITSLICE = 2,  /* bitsliced: 32 blocks per 32-bit word */
+    AES_VARIANT_VPERM = 3      /* no memory tables: the S-box through GF(2^4)
+                                  with 16-entry nibble lookups by v_perm_b32
+                                  (Hamburg's vector-permute AES, CHES 2009) */
 } aes_variant_t;
 
 /* Launch shape.  Zero in any field means "tuned default".
  *   variant          aes_variant_t
  *   blocks_per_lane  16-byte blocks one lane handles per loop step (1, 2, 4)
- *   wg_size          threads per workgroup (multiple of 64, <= 1024)
+ *   wg_size          threads per workgroup (multiple of 64, <= 1024; the
+ *                    bitsliced and vector-permute kernels: 64..256)
  *   grid             workgroups launched (persistent grid-stride loop)
  *   lds_copies       T-table replication (32 or 64 copies per table), T-table only
  *   lds_tables       T-tables held in LDS, T-table only: 4 (T0..T3, 32 copies,
@@ -142,8 +146,9 @@ int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[12], uint32_
 /* The launch shape aes_ctr_crypt_cfg would use for a len-byte message with
  * this key size and cfg (NULL = defaults): the default shape, or the tune
  * cache's entry for the nearest size, overridden by cfg's non-zero fields,
- * with the grid clamped to the work.  All fields of *out are set (variant 1
- * or 2, never AUTO; lds_copies and lds_tables 0 for the bitsliced kernel).  Host only; it
+ * with the grid clamped to the work.  All fields of *out are set (variant 1,
+ * 2 or 3, never AUTO; lds_copies and lds_tables 0 for the kernels without
+ * T-tables).  Host only; it
  * needs the current device's CU count.  Errors: AES_EINVAL (null out, key
  * size not 128/256, bad cfg), AES_EDEVICE. */
 int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_cfg_t *cfg, aes_launch_cfg_t *out);
@@ -226,15 +231,26 @@ typedef struct {
     uint64_t budget_bytes;      /* bytes in flight (0 = 4 GiB): the buffers of
                                    every admitted request (input and output,
                                    counted once when in place; a hash request's
-                                   message and digest) plus its descriptor     */
+                                   message and digest) plus its staged records
+                                   (aes_engine_request_overhead() bytes for a
+                                   cipher request)                             */
     int32_t n_streams;          /* concurrent batch launches (0 = 2)           */
-    int32_t max_batch_reqs;     /* requests per batch (0 = 4096; a larger
-                                   batch is cut into launches of 4096)         */
+    int32_t max_batch_reqs;     /* requests per launch (0, or more than 4096,
+                                   = 4096)                                     */
     uint64_t max_batch_bytes;   /* payload bytes per launch (0 = 256 MiB or the
                                    budget if smaller; a larger request runs
                                    alone)                                      */
-    int32_t key_slots;          /* unused (>= 0): every descriptor carries its
-                                   own expanded key schedule                   */
+    int32_t key_slots;          /* resident key schedules (0 .. 65536; 0 = none):
+                                   the engine keeps this many expanded keys in
+                                   a device table of its own (256 bytes each).
+                                   A request whose key is resident is launched
+                                   with a slot index instead of its schedule;
+                                   a request whose key is not carries it
+                                   inline and, when a slot is free or the
+                                   least recently used slot is not read by a
+                                   launch in flight, installs it there for
+                                   later requests.  Outputs do not depend on
+                                   it.                                         */
     int32_t host_buffers;       /* 1: in/out are pinned host memory
                                    (hipHostMalloc) that the kernel reads and
                                    writes directly over PCIe (zero-copy)       */
@@ -251,12 +267,16 @@ typedef struct {
     double p50_us, p99_us, p999_us; /* arrival (submit) -> completion seen by the poller */
     double busy_s;                  /* wall time with at least one launch in flight */
     double max_us;                  /* slowest request, same clock as p50_us */
-    uint64_t key_hits;              /* cipher requests whose key schedule was already
-                                       resident in a key slot (key_slots > 0) */
-    uint64_t key_misses;            /* ... that had to install it (evicting the least
-                                       recently used unreferenced slot) or, with
-                                       every slot referenced, carried it inline */
+    uint64_t key_hits;              /* cipher requests launched with their key read
+                                       from a resident slot (key_slots > 0)    */
+    uint64_t key_misses;            /* cipher requests launched with their key inline
+                                       (key_slots > 0): a key not resident yet, or
+                                       one whose install was still in flight   */
 } aes_stats_t;
+
+/* Bytes the admission budget charges a cipher request beyond its buffers:
+ * its descriptor record and an inline key record (64 + 256). */
+uint64_t aes_engine_request_overhead(void);
 
 /* Create an engine (cfg may be NULL = defaults).  Starts its driver thread,
  * which forms and launches batches and polls their completion events.

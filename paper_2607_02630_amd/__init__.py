@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _native as N
-from ._native import (AES_VARIANT_AUTO, AES_VARIANT_BITSLICE, AES_VARIANT_TTABLE,  # noqa: F401
+from ._native import (AES_VARIANT_AUTO, AES_VARIANT_BITSLICE, AES_VARIANT_TTABLE, AES_VARIANT_VPERM,  # noqa: F401
                       aes_batch_cfg_t, aes_ctr_desc_t, aes_engine_cfg_t, aes_launch_cfg_t,
                       aes_sched_t, aes_stats_t)
 
@@ -90,7 +90,8 @@ def _nonce(nonce: bytes) -> bytes:
 def launch_cfg(variant: int = 0, blocks_per_lane: int = 0, wg_size: int = 0, grid: int = 0,
                lds_copies: int = 0, lds_tables: int = 0) -> aes_launch_cfg_t:
     """Launch shape for aes_ctr_crypt (aes_launch_cfg_t); zero fields keep the
-    default.  variant: AES_VARIANT_TTABLE (1) or AES_VARIANT_BITSLICE (2);
+    default.  variant: AES_VARIANT_TTABLE (1), AES_VARIANT_BITSLICE (2) or
+    AES_VARIANT_VPERM (3);
     lds_copies / lds_tables: the T-table layout in LDS, 32 or 64 copies of 4
     or 2 tables (64 copies only with 2 tables)."""
     c = aes_launch_cfg_t()

@@ -28,6 +28,7 @@ AES_FLAG_SHA256 = 1
 AES_VARIANT_AUTO = 0
 AES_VARIANT_TTABLE = 1
 AES_VARIANT_BITSLICE = 2
+AES_VARIANT_VPERM = 3
 
 
 class aes_sched_t(ctypes.Structure):
@@ -104,6 +105,7 @@ SIGNATURES = {
     "aes_engine_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(aes_stats_t)]),
     "aes_engine_reset_stats": (ctypes.c_int, [ctypes.c_void_p]),
     "aes_engine_completion_fd": (ctypes.c_int, [ctypes.c_void_p]),
+    "aes_engine_request_overhead": (ctypes.c_uint64, []),
     "aes_ctr_launch_shape": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(aes_launch_cfg_t),
                                             ctypes.POINTER(aes_launch_cfg_t)]),
     "sha256_batch": (ctypes.c_int, [ctypes.POINTER(sha256_desc_t), ctypes.c_size_t, ctypes.c_void_p]),

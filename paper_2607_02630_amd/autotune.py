@@ -2,15 +2,20 @@
 
 For each kernel variant, key size and message size of the sweep workloads
 (4 KiB .. 8 MiB and 256 MiB), every candidate shape is run on the workload's
-seeded input and its output digest is compared with the stored digest the
-oracle wrote (tests/golden/ctr_digests.json) -- a candidate that is not
-bit-exact is discarded -- then timed as K launches replayed from a captured
+seeded input and its output digest is compared with the expected digest in
+the file given by --golden (written by the oracle) -- a candidate that is not
+bit-exact stops the run -- then timed as K launches replayed from a captured
 graph over buffers larger than the Infinity Cache.  The fastest shape per
 (variant, key size, size) is written to the cache, which libaesctr.so reads
-(AESCTR_TUNE_CACHE or tune_cache.json next to the library).  The batch
-kernel's tile size and blocks per lane are tuned on the 4096-request batch.
+(AESCTR_TUNE_CACHE or tune_cache.json next to the library).
 
-Usage: python -m paper_2607_02630_amd.autotune [--quick] [--sizes B,B,...] [--no-batch] [--out PATH]
+The batch kernel's tile sizing (tiles per CU, largest tile) and blocks per
+lane are tuned on the 4096-request batch workload, encrypting zero payloads
+so that the output is the keystream: each candidate's sampled keystream
+blocks must hash to the digest in --golden.
+
+Usage: python -m paper_2607_02630_amd.autotune --golden PATH [--quick] [--sizes B,B,...]
+       [--no-batch] [--out PATH] [--report PATH]
 """
 from __future__ import annotations
 
@@ -28,9 +33,9 @@ ROOT = os.path.dirname(HERE)
 MiB = 1 << 20
 
 
-def _golden():
-    with open(os.path.join(ROOT, "tests", "golden", "ctr_digests.json")) as f:
-        return json.load(f)["sweep"]
+def _load_golden(path: str) -> dict:
+    with open(path) as f:
+        return json.load(f)
 
 
 def candidates(variant: int, quick: bool):
@@ -44,7 +49,7 @@ def candidates(variant: int, quick: bool):
                 yield dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w, grid=gm)
     else:
         for w, gm in itertools.product((64, 128, 256), (1, 2, 4)):
-            yield dict(variant=2, wg_size=w, grid=gm)
+            yield dict(variant=variant, wg_size=w, grid=gm)
 
 
 def time_shape(torch, A, sched, nonce, ins, outs, cfg, steps):
@@ -69,6 +74,10 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(HERE, "tune_cache.json"))
     ap.add_argument("--sizes", default="", help="comma-separated sweep sizes in bytes (default: all)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-kernel tile search")
+    ap.add_argument("--golden", required=True,
+                    help="JSON of expected digests written by the oracle (sweep digests and the "
+                         "batch workload's sampled keystream digest)")
+    ap.add_argument("--report", default="", help="also write every candidate's timing here (JSON)")
     args = ap.parse_args(argv)
     sys.path.insert(0, ROOT)
     import torch
@@ -76,14 +85,15 @@ def main(argv=None):
     import paper_2607_02630_amd as A
 
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    gold = _golden()
+    golden = _load_golden(args.golden)
+    gold = golden["sweep"]
     sizes = [64 * 1024, MiB, 8 * MiB, W.BIG_SIZE] if args.quick else W.SWEEP_SIZES + [W.BIG_SIZE]
     if args.sizes:
         sizes = [int(x) for x in args.sizes.split(",")]
         unknown = [x for x in sizes if f"128/{x}" not in gold]
         if unknown:
             raise SystemExit(f"no stored digests for sizes {unknown}")
-    entries, report = [], []
+    entries, report, tried = [], [], []
     for bits in (128, 256):
         key, nonce = W.sweep_key(bits)
         sched = A.aes_expand_key(key)
@@ -94,7 +104,7 @@ def main(argv=None):
             ins = [src.clone() for _ in range(nbuf)]
             outs = [torch.empty_like(src) for _ in range(nbuf)]
             steps = max(10, min(500, int(2e9 / size)))
-            for variant in (1, 2):
+            for variant in (1, 2, 3):
                 best = None
                 for kw in candidates(variant, args.quick):
                     grid = kw.pop("grid")
@@ -106,6 +116,7 @@ def main(argv=None):
                         raise SystemExit(f"candidate {kw} is not bit-exact at AES-{bits} {size} B")
                     ms = time_shape(torch, A, sched, nonce, ins, outs, cfg, steps)
                     kw["grid"] = grid
+                    tried.append({"key_bits": bits, "size": size, **kw, "us": round(ms * 1e3, 3)})
                     if best is None or ms < best[0]:
                         best = (ms, kw)
                 ms, kw = best
@@ -118,56 +129,79 @@ def main(argv=None):
                 print(json.dumps(report[-1]), flush=True)
             del ins, outs, src
             torch.cuda.empty_cache()
+    batch_tried = []
     if not args.no_batch:
-        entries.append(tune_batch(torch, A, W, cus))
+        entry, batch_tried = tune_batch(torch, A, W, cus, golden["batch_keystream_samples"]["sha256"])
+        entries.append(entry)
     with open(args.out, "w") as f:
-        json.dump({"generated": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries,
-                   "measured": report}, f, indent=1)
+        json.dump({"generated": time.strftime("%Y-%m-%d %H:%M:%S"), "device": torch.cuda.get_device_name(0),
+                   "entries": entries, "measured": report}, f, indent=1)
         f.write("\n")
     print(f"wrote {args.out}")
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump({"single": tried, "batch": batch_tried, "winners": report}, f, indent=1)
+            f.write("\n")
 
 
-def tune_batch(torch, A, W, cus):
-    """Tile size and blocks per lane of the batch kernel on the 4096-request
-    batch; each candidate must reproduce the first candidate's output."""
+def sampled_keystream_digest(torch, reqs, offs, dst) -> str:
+    """SHA-256 over the sampled blocks of every request (blocks 0, n//2 and
+    n-1, each once, the last cut to the tail), in request order, read from
+    the outputs of a batch run on zero payloads."""
+    idx = []
+    for r, o in zip(reqs, offs):
+        nb = (r.length + 15) // 16
+        for j in sorted({0, nb // 2, nb - 1}):
+            n = min(16, r.length - 16 * j)
+            idx.extend(range(o + 16 * j, o + 16 * j + n))
+    sel = dst[torch.tensor(idx, dtype=torch.int64, device=dst.device)]
+    return hashlib.sha256(sel.cpu().numpy().tobytes()).hexdigest()
+
+
+def tune_batch(torch, A, W, cus, expect: str):
+    """Tile sizing (tiles per CU and the largest tile) and blocks per lane of
+    the batch kernel on the 4096-request batch, on zero payloads: every
+    candidate's sampled keystream must hash to `expect`."""
     reqs = W.batch_requests()
     offs, pos = [], 0
     for r in reqs:
         offs.append(pos)
         pos += (r.length + 255) // 256 * 256
-    src = W.device_payload(pos, 4242)
+    src = torch.zeros(pos, dtype=torch.uint8, device="cuda")
     dst = torch.zeros_like(src)
     scheds = [A.aes_expand_key(r.key) for r in reqs]
     objs = [A.Request(s, r.nonce, r.ctr0, src.data_ptr() + o, dst.data_ptr() + o, r.length)
             for s, r, o in zip(scheds, reqs, offs)]
     arr = A.make_desc_array(objs)
-    ref = None
-    best = None
-    for tile, bpl in itertools.product((4096, 16384, 65536), (1, 2)):
+    total = sum(r.length for r in reqs)
+    best, tried = None, []
+    for tpc, max_tile, bpl in itertools.product((8, 16, 32), (65536, 262144, 1 << 20), (1, 2)):
+        tile = max(2048, min(max_tile, (total // (tpc * cus) + 2047) // 2048 * 2048))
         cfg = A.batch_cfg(tile_bytes=tile, blocks_per_lane=bpl)
         dst.zero_()
         A.aes_ctr_crypt_batch(objs, cfg=cfg, descs=arr)
         torch.cuda.synchronize()
-        if ref is None:
-            ref = dst.clone()
-        elif not torch.equal(ref, dst):
-            raise SystemExit(f"batch candidate tile={tile} bpl={bpl} changed the output")
+        got = sampled_keystream_digest(torch, reqs, offs, dst)
+        if got != expect:
+            raise SystemExit(f"batch candidate tiles/CU={tpc} max tile={max_tile} bpl={bpl} is not bit-exact")
         times = []
-        for _ in range(3):
+        for _ in range(5):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             A.aes_ctr_crypt_batch(objs, cfg=cfg, descs=arr)
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
-        ms = sorted(times)[1]
-        print(json.dumps({"batch_tile_bytes": tile, "bpl": bpl, "ms": round(ms, 3)}), flush=True)
+        ms = sorted(times)[2]
+        rec = {"tiles_per_cu": tpc, "max_tile_bytes": max_tile, "tile_bytes": tile, "bpl": bpl, "ms": round(ms, 3)}
+        tried.append(rec)
+        print(json.dumps({"batch": rec}), flush=True)
         if best is None or ms < best[0]:
-            best = (ms, tile, bpl)
-    del src, dst, ref
+            best = (ms, tpc, max_tile, bpl)
+    del src, dst
     torch.cuda.empty_cache()
-    return {"variant": 10, "key_bits": 0, "size_log2": 0, "bpl": best[2], "wg": 1024, "grid_per_cu": 1,
-            "copies": 0, "tile_bytes": best[1]}
+    return ({"variant": 10, "key_bits": 0, "size_log2": 0, "bpl": best[3], "wg": 1024, "grid_per_cu": 1,
+             "copies": 0, "tiles_per_cu": best[1], "max_tile_bytes": best[2]}, tried)
 
 
 if __name__ == "__main__":

@@ -133,7 +133,15 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         } else {
             sh.bpl = 1; sh.wg = 256;
         }
+    } else if (sh.variant == AES_VARIANT_BITSLICE) {
+        sh.bpl = 1;
+        sh.wg = 256;
+        sh.copies = 0;
+        sh.tables = 0;
+        sh.grid = 2 * di.num_cus;
     } else {
+        // Vector-permute kernel: one block per lane, bound by VALU issue;
+        // eight waves per CU keep every SIMD busy.
         sh.bpl = 1;
         sh.wg = 256;
         sh.copies = 0;
@@ -191,7 +199,7 @@ namespace {
 int check_cfg(const aes_launch_cfg_t *cfg, int *variant)
 {
     *variant = cfg ? cfg->variant : AES_VARIANT_AUTO;
-    if (*variant < AES_VARIANT_AUTO || *variant > AES_VARIANT_BITSLICE)
+    if (*variant < AES_VARIANT_AUTO || *variant > AES_VARIANT_VPERM)
         return AES_EINVAL;
     if (cfg) {
         if (cfg->blocks_per_lane != 0 && cfg->blocks_per_lane != 1 && cfg->blocks_per_lane != 2 &&
@@ -228,6 +236,12 @@ Shape resolve_shape(int variant, int key_bits, uint64_t len, const aes_launch_cf
         else if (sh.tables == 0)
             sh.tables = 4;
     }
+    if (sh.variant != AES_VARIANT_TTABLE) {
+        sh.copies = 0;
+        sh.tables = 0;
+    }
+    if (sh.variant == AES_VARIANT_VPERM)
+        sh.bpl = 1;     // one block per lane, whatever cfg asks
     clamp_grid(&sh, len);
     // Per-wave first-chunk group constants pay off when two workgroups with
     // the 64 KiB image share each CU (8 MiB AES-128: 7.64-7.69 against
@@ -285,6 +299,12 @@ extern "C" int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[1
         return rc;
     const Shape sh = resolve_shape(variant, sched->key_bits, len, cfg, di);
 
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (sh.variant == AES_VARIANT_VPERM) {
+        VpArgs va;
+        make_vperm_args(*sched, nonce, ctr0, in, out, len, &va);
+        return launch_ctr_vperm(va, sched->nr, sh, st);
+    }
     KeyMaterial km;
     make_key_material(*sched, nonce, &km);
     CtrArgs a{};
@@ -295,7 +315,6 @@ extern "C" int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[1
     a.x0 = km.x0;
     memcpy(a.k1, km.k1, sizeof(a.k1));
     memcpy(a.rk, km.rk, sizeof(a.rk));
-    hipStream_t st = static_cast<hipStream_t>(stream);
     if (sh.variant == AES_VARIANT_BITSLICE)
         return launch_ctr_bitslice(a, km.nr, sh, st);
     return launch_ctr_ttable(a, km.nr, sh, st);

@@ -2,16 +2,17 @@
 // captured-graph launch.
 //
 // Per (device, stream) the library keeps a context: a device table (header +
-// up to kMaxBatch descriptors) and a ring of pinned host staging slots, each
-// with an executable HIP graph of two nodes -- the host-to-device copy of that
-// slot into the table, then the persistent batch kernel.  A call fills a free
-// slot, sets its graph's copy size, and launches the graph on the caller's
-// stream; nothing is re-captured between calls.  A slot (and its graph) is
-// reused only after the event recorded behind its last launch completes, so
-// no update touches a graph still in flight.  The tile counter the kernel
-// claims work from is part of every upload (0), so no memset node is needed.
-// The call cannot itself be captured into a caller's graph (its staging would
-// be rewritten by later calls): on a capturing stream it returns AES_EINVAL.
+// up to kMaxBatch descriptors, their inline keys and key installs) and a ring
+// of pinned host staging slots, each with an executable HIP graph of two
+// nodes -- the host-to-device copy of that slot into the table, then the
+// persistent batch kernel.  A call fills a free slot, sets its graph's copy
+// size, and launches the graph on the caller's stream; nothing is
+// re-captured between calls.  A slot (and its graph) is reused only after the
+// event recorded behind its last launch completes, so no update touches a
+// graph still in flight.  The tile counter the kernel claims work from is
+// part of every upload (0), so no memset node is needed.  The call cannot
+// itself be captured into a caller's graph (its staging would be rewritten
+// by later calls): on a capturing stream it returns AES_EINVAL.
 #include <map>
 #include <memory>
 #include <mutex>
@@ -27,7 +28,7 @@ namespace aesctr {
 namespace {
 
 constexpr int kSlots = 4;
-constexpr size_t kTableBytes = sizeof(BatchHeader) + sizeof(BatchDesc) * kMaxBatch;
+constexpr size_t kTableBytes = kMaxTableBytes;
 
 // Descriptors per part of the host's parallel validation.
 constexpr size_t kCheckGrain = 4096;
@@ -155,9 +156,10 @@ int build_graph(BatchCtx *c, int s, int grid, int bpl)
 
 }  // namespace
 
-// Completes staging slot `buf` whose n records are written: assigns first
-// tiles and fills the header.  Returns the bytes to upload, or 0 if the tile
-// count would overflow.
+// Completes a staged table at buf: n descriptors, header.n_keys inline keys
+// and header.n_install installs written.  Assigns first tiles and fills the
+// rest of the header.  Returns the bytes to upload, or 0 if the tile count
+// would overflow.
 size_t finish_stage(uint8_t *buf, size_t n, uint32_t tile_blocks)
 {
     BatchHeader *h = reinterpret_cast<BatchHeader *>(buf);
@@ -170,12 +172,14 @@ size_t finish_stage(uint8_t *buf, size_t n, uint32_t tile_blocks)
         if (tiles > 0x7fffffffu)
             return 0;
     }
-    memset(h, 0, sizeof(*h));
     h->n = static_cast<uint32_t>(n);
     h->total_tiles = static_cast<uint32_t>(tiles);
     h->tile_blocks = tile_blocks;
     h->next = 0;
-    return sizeof(BatchHeader) + n * sizeof(BatchDesc);
+    h->keys_off = static_cast<uint32_t>(batch_keys_off(n));
+    h->install_off = static_cast<uint32_t>(batch_install_off(n, h->n_keys));
+    memset(h->pad, 0, sizeof(h->pad));
+    return batch_table_bytes(n, h->n_keys, h->n_install);
 }
 
 namespace {
@@ -183,20 +187,14 @@ namespace {
 // Records per part of the host's parallel record building.
 constexpr size_t kRecordGrain = 256;
 
-// Stages n records, produced by fill(dst, first, m) for records
-// [first, first + m), and launches them (kMaxBatch per launch) through the
-// slot's captured graph or a plain copy + launch.
 // A batch of at most kSmallBatch requests goes in the kernel's argument block
 // (no staging slot, no upload).  Returns AES_OK, AES_ERANGE or AES_EDEVICE.
-template <class Fill>
-int launch_small(hipStream_t st, size_t n, uint32_t tile_blocks, int grid, int bpl, Fill fill)
+int launch_small(hipStream_t st, const LaunchSpec &spec, uint32_t tile_blocks, int grid, int bpl)
 {
-    BatchDesc recs[kSmallBatch];
-    fill(recs, 0, n);
     SmallBatchArgs args{};
     uint64_t tiles = 0;
-    for (size_t i = 0; i < n; ++i) {
-        const BatchDesc &d = recs[i];
+    for (size_t i = 0; i < spec.n; ++i) {
+        const BatchDesc &d = spec.descs[i];
         SmallRec &r = args.r[i];
         r.in = d.in;
         r.out = d.out;
@@ -206,75 +204,113 @@ int launch_small(hipStream_t st, size_t n, uint32_t tile_blocks, int grid, int b
         r.nr = d.nr;
         r.aligned = d.aligned;
         memcpy(r.k1, d.k1, sizeof(r.k1));
-        memcpy(r.rk, d.rk, sizeof(r.rk));
+        r.key = d.key;
+        r.install = kNoInstall;
+        if (!(d.key & kKeyResident)) {
+            memcpy(r.rk, spec.keys[d.key].rk, sizeof(r.rk));
+            for (size_t j = 0; j < spec.n_install; ++j)
+                if (spec.installs[j].key == d.key)
+                    r.install = spec.installs[j].slot;
+        }
         r.tile0 = static_cast<uint32_t>(tiles);
         tiles += ((d.len + 15) / 16 + tile_blocks - 1) / tile_blocks;
         if (tiles > 0x7fffffffu)
             return AES_ERANGE;
     }
-    args.n = static_cast<uint32_t>(n);
+    // An install names one inline key; two records sharing that key must not
+    // both write the slot: keep the first.
+    for (size_t i = 0; i < spec.n; ++i)
+        for (size_t j = 0; j < i; ++j)
+            if (args.r[i].install != kNoInstall && args.r[i].install == args.r[j].install)
+                args.r[i].install = kNoInstall;
+    args.n = static_cast<uint32_t>(spec.n);
     args.total_tiles = static_cast<uint32_t>(tiles);
     args.tile_blocks = tile_blocks;
+    args.resident = spec.resident;
     return launch_ctr_batch_small(args, grid, 1024, bpl, st);
 }
 
-template <class Fill>
-int launch_filled(int device, hipStream_t st, size_t n, int tile_bytes, int grid, int bpl, bool use_graph,
-                  bool allow_small, Fill fill)
+// Takes the context's next staging slot once its last launch has finished.
+int take_slot(BatchCtx *c, int *slot)
 {
-    if (allow_small && n <= kSmallBatch)
-        return launch_small(st, n, static_cast<uint32_t>(tile_bytes / 16), grid, bpl, fill);
-    int rc;
-    BatchCtx *c = get_ctx(device, st, &rc);
-    if (!c)
-        return rc;
-    const uint32_t tile_blocks = static_cast<uint32_t>(tile_bytes / 16);
-    std::lock_guard<std::mutex> lk(c->mu);
-    for (size_t first = 0; first < n; first += kMaxBatch) {
-        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
-        const int slot = c->next_slot;
-        c->next_slot = (c->next_slot + 1) % kSlots;
-        if (c->used[slot] && hipEventSynchronize(c->done[slot]) != hipSuccess) {
-            note_device_error(hipGetLastError());
-            return AES_EDEVICE;
-        }
-        BatchDesc *out = reinterpret_cast<BatchDesc *>(c->staging[slot] + sizeof(BatchHeader));
-        HostPool::get().parallel_for(m, kRecordGrain, [&](size_t, size_t b, size_t e) {
-            fill(out + b, first + b, e - b);
-        });
-        const size_t bytes = finish_stage(c->staging[slot], m, tile_blocks);
-        if (bytes == 0)
-            return AES_ERANGE;
-        if (use_graph) {
-            SlotGraph &sg = c->g[slot];
-            if (!sg.exec || sg.grid != grid || sg.bpl != bpl) {
-                if ((rc = build_graph(c, slot, grid, bpl)) != AES_OK)
-                    return rc;
-            }
-            if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
-                                                  hipMemcpyHostToDevice) != hipSuccess ||
-                hipGraphLaunch(sg.exec, st) != hipSuccess) {
-                note_device_error(hipGetLastError());
-                return AES_EDEVICE;
-            }
-        } else {
-            if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
-                note_device_error(hipGetLastError());
-                return AES_EDEVICE;
-            }
-            if ((rc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, st)) != AES_OK)
-                return rc;
-        }
-        if (hipEventRecord(c->done[slot], st) != hipSuccess) {
-            note_device_error(hipGetLastError());
-            return AES_EDEVICE;
-        }
-        c->used[slot] = true;
+    *slot = c->next_slot;
+    c->next_slot = (c->next_slot + 1) % kSlots;
+    if (c->used[*slot] && hipEventSynchronize(c->done[*slot]) != hipSuccess) {
+        note_device_error(hipGetLastError());
+        return AES_EDEVICE;
     }
     return AES_OK;
 }
 
+// Uploads the first `bytes` of staging slot `slot` into the device table and
+// launches the batch kernel on st, through the slot's captured graph or a
+// plain copy + launch, then marks the slot busy until that work finishes.
+int submit_slot(BatchCtx *c, int slot, size_t bytes, hipStream_t st, int grid, int bpl, bool use_graph)
+{
+    int rc;
+    if (use_graph) {
+        SlotGraph &sg = c->g[slot];
+        if (!sg.exec || sg.grid != grid || sg.bpl != bpl) {
+            if ((rc = build_graph(c, slot, grid, bpl)) != AES_OK)
+                return rc;
+        }
+        if (hipGraphExecMemcpyNodeSetParams1D(sg.exec, sg.copy_node, c->dev_table, c->staging[slot], bytes,
+                                              hipMemcpyHostToDevice) != hipSuccess ||
+            hipGraphLaunch(sg.exec, st) != hipSuccess) {
+            note_device_error(hipGetLastError());
+            return AES_EDEVICE;
+        }
+    } else {
+        if (hipMemcpyAsync(c->dev_table, c->staging[slot], bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+            note_device_error(hipGetLastError());
+            return AES_EDEVICE;
+        }
+        if ((rc = launch_ctr_batch(c->dev_table, grid, 1024, bpl, st)) != AES_OK)
+            return rc;
+    }
+    if (hipEventRecord(c->done[slot], st) != hipSuccess) {
+        note_device_error(hipGetLastError());
+        return AES_EDEVICE;
+    }
+    c->used[slot] = true;
+    return AES_OK;
+}
+
 }  // namespace
+
+int launch_spec(int device, hipStream_t st, const LaunchSpec &spec, int tile_bytes, int grid, int bpl,
+                bool use_graph, bool allow_small)
+{
+    const uint32_t tile_blocks = static_cast<uint32_t>(tile_bytes / 16);
+    if (spec.n == 0)
+        return AES_OK;
+    if (spec.n > static_cast<size_t>(kMaxBatch) || spec.n_keys > static_cast<size_t>(kMaxBatch) ||
+        spec.n_install > static_cast<size_t>(kMaxBatch))
+        return AES_EINVAL;
+    if (allow_small && spec.n <= kSmallBatch)
+        return launch_small(st, spec, tile_blocks, grid, bpl);
+    int rc;
+    BatchCtx *c = get_ctx(device, st, &rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    int slot;
+    if ((rc = take_slot(c, &slot)) != AES_OK)
+        return rc;
+    uint8_t *buf = c->staging[slot];
+    BatchHeader *h = reinterpret_cast<BatchHeader *>(buf);
+    memset(h, 0, sizeof(*h));
+    h->n_keys = static_cast<uint32_t>(spec.n_keys);
+    h->n_install = static_cast<uint32_t>(spec.n_install);
+    h->resident = spec.resident;
+    memcpy(buf + sizeof(BatchHeader), spec.descs, spec.n * sizeof(BatchDesc));
+    memcpy(buf + batch_keys_off(spec.n), spec.keys, spec.n_keys * sizeof(KeyRec));
+    memcpy(buf + batch_install_off(spec.n, spec.n_keys), spec.installs, spec.n_install * sizeof(InstallRec));
+    const size_t bytes = finish_stage(buf, spec.n, tile_blocks);
+    if (bytes == 0)
+        return AES_ERANGE;
+    return submit_slot(c, slot, bytes, st, grid, bpl, use_graph);
+}
 
 void release_batch_stream(int device, hipStream_t st)
 {
@@ -303,17 +339,36 @@ void release_batch_stream(int device, hipStream_t st)
 
 uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus)
 {
-    // About sixteen tiles per CU (one per wave of a workgroup), between 2 KiB
-    // (one wave step: 64 lanes x 2 blocks) and 64 KiB.  Measured on MI355X:
-    // on the 4096-request workload 64 KiB tiles (3.59 ms) beat 16 KiB (3.67)
-    // and 4 KiB (12.8, when every tile was claimed with an atomic); small
-    // batches need small tiles to reach many CUs.
+    // About kTilesPerCu tiles per CU (one per wave of a workgroup), between
+    // 2 KiB (one wave step: 64 lanes x 2 blocks) and kMaxTile, multiples of
+    // 2 KiB; the tune cache's batch entry may set both constants.  Measured on
+    // MI355X: on the 4096-request workload 64 KiB tiles (3.59 ms) beat 16 KiB
+    // (3.67) and 4 KiB (12.8, when every tile was claimed with an atomic);
+    // small batches need small tiles to reach many CUs.
+    constexpr uint64_t kTilesPerCu = 16, kMaxTile = 65536;
+    uint64_t tpc = kTilesPerCu, max_tile = kMaxTile;
+    TuneEntry te;
+    if (tune_lookup_batch(&te)) {
+        if (te.tiles_per_cu >= 1 && te.tiles_per_cu <= 1024)
+            tpc = static_cast<uint64_t>(te.tiles_per_cu);
+        if (te.max_tile_bytes >= 2048 && te.max_tile_bytes <= (1 << 24) && te.max_tile_bytes % 2048 == 0)
+            max_tile = static_cast<uint64_t>(te.max_tile_bytes);
+    }
     const uint64_t cus = static_cast<uint64_t>(num_cus > 0 ? num_cus : 1);
-    uint64_t tile = (batch_bytes / (16 * cus) + 2047) & ~uint64_t(2047);
-    return tile < 2048 ? 2048 : tile > 65536 ? 65536 : tile;
+    uint64_t tile = (batch_bytes / (tpc * cus) + 2047) & ~uint64_t(2047);
+    return tile < 2048 ? 2048 : tile > max_tile ? max_tile : tile;
 }
 
-void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o)
+int batch_blocks_per_lane()
+{
+    TuneEntry te;
+    return tune_lookup_batch(&te) && (te.bpl == 1 || te.bpl == 2) ? te.bpl : 2;
+}
+
+namespace {
+
+// Descriptor (key field left 0) and round keys of one validated request.
+void make_record(const aes_ctr_desc_t &d, BatchDesc *o, KeyRec *k)
 {
     KeyMaterial km;
     make_key_material(*d.sched, d.nonce, &km);
@@ -323,10 +378,18 @@ void make_batch_record(const aes_ctr_desc_t &d, BatchDesc *o)
     o->len = d.len;
     o->ctr0 = d.ctr0;
     o->x0 = km.x0;
-    o->nr = static_cast<uint32_t>(km.nr);
+    o->nr = static_cast<uint16_t>(km.nr);
     o->aligned = ((o->in | o->out) & 15) == 0;
     memcpy(o->k1, km.k1, sizeof(o->k1));
-    memcpy(o->rk, km.rk, sizeof(o->rk));
+    memset(k, 0, sizeof(*k));
+    memcpy(k->rk, km.rk, sizeof(km.rk));
+}
+
+}  // namespace
+
+void make_batch_record(const aes_ctr_desc_t &d, RequestRec *o)
+{
+    make_record(d, &o->d, &o->key);
 }
 
 int check_desc(const aes_ctr_desc_t &d)
@@ -337,15 +400,6 @@ int check_desc(const aes_ctr_desc_t &d)
     if (d.flags != 0)
         return AES_EINVAL;
     return check_buffers(d.in, d.out, d.len);
-}
-
-int launch_records(int device, hipStream_t st, const BatchDesc *recs, size_t n, int tile_bytes, int grid,
-                   int bpl, bool use_graph, bool allow_small)
-{
-    return launch_filled(device, st, n, tile_bytes, grid, bpl, use_graph, allow_small,
-                         [recs](BatchDesc *dst, size_t first, size_t m) {
-                             memcpy(dst, recs + first, m * sizeof(BatchDesc));
-                         });
 }
 
 }  // namespace aesctr
@@ -381,14 +435,9 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
             return scan[p].rc;
         total_bytes += scan[p].bytes;
     }
-    // Tile size 0 = sized to the batch (batch_tile_bytes); two blocks per lane.
-    BatchShape sh{0, 1024, 0, 2, 1};
-    TuneEntry te;
-    if (tune_lookup_batch(&te)) {
-        sh.bpl = te.bpl <= 2 ? te.bpl : 1;
-        if (te.tile_bytes >= 1024 && te.tile_bytes % 1024 == 0)
-            sh.tile_bytes = te.tile_bytes;
-    }
+    // Tile size 0 = sized to the batch (batch_tile_bytes); two blocks per
+    // lane unless the tune cache says otherwise.
+    BatchShape sh{0, 1024, 0, batch_blocks_per_lane(), 1};
     if (cfg) {
         if (cfg->tile_bytes < 0 || (cfg->tile_bytes && (cfg->tile_bytes % 1024 != 0 || cfg->tile_bytes > (1 << 26))))
             return AES_EINVAL;
@@ -420,12 +469,54 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
 
     if (sh.tile_bytes == 0)
         sh.tile_bytes = static_cast<int>(batch_tile_bytes(total_bytes, di.num_cus));
-    // Records are built straight into the pinned staging slot.
-    return launch_filled(di.ordinal, st, n, sh.tile_bytes, sh.grid, sh.bpl, sh.use_graph != 0, true,
-                         [desc](BatchDesc *dst, size_t first, size_t m) {
-                             for (size_t i = 0; i < m; ++i)
-                                 make_batch_record(desc[first + i], dst + i);
-                         });
+    const uint32_t tile_blocks = static_cast<uint32_t>(sh.tile_bytes / 16);
+
+    // At most kSmallBatch requests: records in the kernel arguments.
+    if (n <= kSmallBatch) {
+        BatchDesc descs[kSmallBatch];
+        KeyRec keys[kSmallBatch];
+        for (size_t i = 0; i < n; ++i) {
+            make_record(desc[i], &descs[i], &keys[i]);
+            descs[i].key = static_cast<uint32_t>(i);
+        }
+        LaunchSpec spec;
+        spec.descs = descs;
+        spec.n = n;
+        spec.keys = keys;
+        spec.n_keys = n;
+        return launch_small(st, spec, tile_blocks, sh.grid, sh.bpl);
+    }
+
+    // Otherwise launches of up to kMaxBatch requests, each request's key
+    // inline.  Records are built straight into the pinned staging slot.
+    BatchCtx *c = get_ctx(di.ordinal, st, &rc);
+    if (!c)
+        return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (size_t first = 0; first < n; first += kMaxBatch) {
+        const size_t m = n - first < static_cast<size_t>(kMaxBatch) ? n - first : kMaxBatch;
+        int slot;
+        if ((rc = take_slot(c, &slot)) != AES_OK)
+            return rc;
+        uint8_t *buf = c->staging[slot];
+        BatchHeader *h = reinterpret_cast<BatchHeader *>(buf);
+        memset(h, 0, sizeof(*h));
+        h->n_keys = static_cast<uint32_t>(m);
+        BatchDesc *out = reinterpret_cast<BatchDesc *>(buf + sizeof(BatchHeader));
+        KeyRec *keys = reinterpret_cast<KeyRec *>(buf + batch_keys_off(m));
+        HostPool::get().parallel_for(m, kRecordGrain, [&](size_t, size_t b, size_t e) {
+            for (size_t i = b; i < e; ++i) {
+                make_record(desc[first + i], out + i, keys + i);
+                out[i].key = static_cast<uint32_t>(i);
+            }
+        });
+        const size_t bytes = finish_stage(buf, m, tile_blocks);
+        if (bytes == 0)
+            return AES_ERANGE;
+        if ((rc = submit_slot(c, slot, bytes, st, sh.grid, sh.bpl, sh.use_graph != 0)) != AES_OK)
+            return rc;
+    }
+    return AES_OK;
 }
 
 extern "C" int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream)

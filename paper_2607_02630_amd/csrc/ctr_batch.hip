@@ -26,6 +26,11 @@ typedef __attribute__((address_space(1))) const u32x4 g_cu32x4;
 typedef __attribute__((address_space(1))) u32x4 g_u32x4;
 typedef __attribute__((address_space(1))) const uint8_t g_cu8;
 typedef __attribute__((address_space(1))) uint8_t g_u8;
+// Round keys are read through the constant address space, so they load with
+// scalar instructions even though workgroup 0 of the same launch writes
+// other slots of the resident table (installs): no launch reads a slot that
+// it, or any launch in flight, writes.
+typedef __attribute__((address_space(4))) const uint32_t c_u32;
 
 // Blocks [b0, b1) of one request.  The loop trip count is the same for every
 // lane (the round-1/2 sharing needs the whole wave), and lane i of each step
@@ -88,10 +93,12 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchLayout> &tt, const C
 
 // Tile t of request R (a BatchDesc in the device table or a SmallRec in the
 // kernel arguments; both wave-uniform, so their fields arrive by scalar
-// loads): the request's key material and pointers, then the tile's blocks.
+// loads) with round keys rk (wave-uniform, read from the launch's inline keys
+// or from a slot of the resident key table): the request's key material and
+// pointers, then the tile's blocks.
 template <int BPL, class Rec>
-__device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, const Rec &R, uint32_t t,
-                                             uint32_t tile_blocks, uint32_t lane)
+__device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, const Rec &R, const uint32_t (&rk)[60],
+                                             uint32_t t, uint32_t tile_blocks, uint32_t lane)
 {
     CtrArgs a;
     a.in = reinterpret_cast<const uint8_t *>(R.in);
@@ -106,7 +113,7 @@ __device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, con
     const uint32_t nrk = 4 * (nr + 1);
 #pragma unroll
     for (int i = 0; i < 60; ++i)
-        a.rk[i] = i < 44 || nrk > 44 ? R.rk[i] : 0;
+        a.rk[i] = i < 44 || nrk > 44 ? rk[i] : 0;
     const uint64_t nblocks = (a.len + 15) >> 4;
     const uint64_t b0 = static_cast<uint64_t>(t - R.tile0) * tile_blocks;
     const uint64_t b1 = b0 + tile_blocks < nblocks ? b0 + tile_blocks : nblocks;
@@ -123,9 +130,20 @@ __device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, con
     }
 }
 
-// table: the uploaded header + descriptors, read-only here (so request fields
-// come in through the scalar cache); counter: the header's `next` word, the
-// only thing the kernel writes besides the outputs.
+// Writes the round keys of key record `src` (64 words) into slot `slot` of
+// the resident table, one word per thread of the workgroup, with vector
+// stores.  No wave of this launch reads that slot (its requests read the
+// inline copy), and no launch in flight reads it either: the host hands a
+// slot out for installing only when nothing references it.
+__device__ __forceinline__ void install_key(uint32_t *resident, uint32_t slot, const uint32_t *src, uint32_t word)
+{
+    resident[64u * slot + word] = src[word];
+}
+
+// table: the uploaded header, descriptors, inline keys and installs,
+// read-only here (so request fields come in through the scalar cache);
+// counter: the header's `next` word.  Besides the outputs the kernel writes
+// only that counter and, in workgroup 0, the installs' resident slots.
 template <int BPL>
 __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__restrict__ table,
                                                              uint32_t *__restrict__ counter)
@@ -138,11 +156,21 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
     const uint32_t n = hdr->n;
     const uint32_t total = hdr->total_tiles;
     const uint32_t tile_blocks = hdr->tile_blocks;
+    const uint32_t *keys = reinterpret_cast<const uint32_t *>(table + hdr->keys_off);
+    uint32_t *resident = reinterpret_cast<uint32_t *>(hdr->resident);
 
     uint32_t tv[kFillStores / kBatchWG];
     fill_read<kBatchLayout, kBatchWG>(tv);
     for (uint32_t i = threadIdx.x; i < n; i += kBatchWG)
         s_tile0[i] = desc[i].tile0;
+    if (blockIdx.x == 0) {
+        const InstallRec *inst = reinterpret_cast<const InstallRec *>(table + hdr->install_off);
+        const uint32_t words = 64u * hdr->n_install;
+        for (uint32_t i = threadIdx.x; i < words; i += kBatchWG) {
+            const InstallRec r = inst[i >> 6];
+            install_key(resident, r.slot, keys + 64u * r.key, i & 63u);
+        }
+    }
     fill_write<kBatchLayout, kBatchWG>(lds, tv);
     __syncthreads();
 
@@ -172,7 +200,19 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
                 hi = mid - 1;
         }
         const uint32_t r = __builtin_amdgcn_readfirstlane(lo);
-        request_tile<BPL>(tt, desc[r], t, tile_blocks, lane);
+        const BatchDesc &R = desc[r];
+        const uint32_t key = R.key;
+        uint32_t rk[60];
+        if (key & kKeyResident) {
+            c_u32 *p = (c_u32 *)(uintptr_t)(resident + 64u * (key & ~kKeyResident));
+#pragma unroll
+            for (int i = 0; i < 60; ++i) rk[i] = p[i];
+        } else {
+            const uint32_t *p = keys + 64u * key;
+#pragma unroll
+            for (int i = 0; i < 60; ++i) rk[i] = p[i];
+        }
+        request_tile<BPL>(tt, R, rk, t, tile_blocks, lane);
         t = waves + __builtin_amdgcn_readfirstlane(claim);
     }
 }
@@ -189,13 +229,19 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_small_kernel(const SmallBa
 
     uint32_t tv[kFillStores / kBatchWG];
     fill_read<kBatchLayout, kBatchWG>(tv);
+    uint32_t *resident = reinterpret_cast<uint32_t *>(args.resident);
+    const uint32_t n = args.n;
+    if (blockIdx.x == 0 && threadIdx.x < 64u * kSmallBatch) {
+        const uint32_t i = threadIdx.x >> 6, w = threadIdx.x & 63u;
+        if (i < n && args.r[i].install != kNoInstall && w < 60u)
+            install_key(resident, args.r[i].install, args.r[i].rk, w);
+    }
     fill_write<kBatchLayout, kBatchWG>(lds, tv);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63;
     TTable<kBatchLayout> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
     const uint32_t waves = gridDim.x * (kBatchWG / 64);
-    const uint32_t n = args.n;
     for (uint32_t t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
          t < args.total_tiles; t += waves) {
         // Last request whose first tile is <= t (skips empty requests).
@@ -203,7 +249,17 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_small_kernel(const SmallBa
         for (uint32_t i = 1; i < n; ++i)
             if (args.r[i].tile0 <= t)
                 r = i;
-        request_tile<BPL>(tt, args.r[r], t, args.tile_blocks, lane);
+        const SmallRec &R = args.r[r];
+        uint32_t rk[60];
+        if (R.key & kKeyResident) {
+            c_u32 *p = (c_u32 *)(uintptr_t)(resident + 64u * (R.key & ~kKeyResident));
+#pragma unroll
+            for (int i = 0; i < 60; ++i) rk[i] = p[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 60; ++i) rk[i] = R.rk[i];
+        }
+        request_tile<BPL>(tt, R, rk, t, args.tile_blocks, lane);
     }
 }
 

@@ -259,3 +259,125 @@ def test_hash_request_validation():
         d.flags = 2                                                    # unknown flag
         d.reserved = 0
         assert A.lib.aes_submit(eng._h, ctypes.byref(d), ctypes.byref(t)) == N.AES_EINVAL
+
+
+def make_tenant_requests(torch, n, n_keys, seed, sizes=(4 * KiB, 64 * KiB, 1 * MiB + 7), mix=(0.5, 0.4, 0.1)):
+    """Requests whose keys repeat: each draws one of n_keys tenant keys (half
+    AES-128, half AES-256), with its own nonce and start counter."""
+    g = np.random.default_rng(seed)
+    keys = [g.bytes(16 if i % 2 == 0 else 32) for i in range(n_keys)]
+    scheds = [lib().aes_expand_key(k) for k in keys]
+    which = g.choice(len(sizes), size=n, p=mix)
+    lens = [int(sizes[k]) for k in which]
+    src = W.device_payload(sum(lens), seed)
+    dst = torch.zeros_like(src)
+    A = lib()
+    reqs, offs, pos = [], [], 0
+    for L in lens:
+        k = int(g.integers(0, n_keys))
+        nonce, ctr0 = g.bytes(12), int(g.integers(0, 1 << 32))
+        reqs.append((keys[k], nonce, ctr0, scheds[k],
+                     A.Request(scheds[k], nonce, ctr0, src.data_ptr() + pos, dst.data_ptr() + pos, L)))
+        offs.append(pos)
+        pos += L
+    torch.cuda.synchronize()
+    return src, dst, reqs, offs, lens
+
+
+@pytest.mark.parametrize("n_keys,slots", [(6, 16), (40, 16)], ids=["fits", "evicts"])
+def test_resident_key_slots(n_keys, slots):
+    """Key schedules resident in the engine's key slots.  Requests reuse a few
+    tenant keys: first one at a time (single-request launches, whose
+    records travel in the kernel arguments, install and then hit slots),
+    then in bursts (launches through the staged table).  With more keys than
+    slots the least recently used ones are evicted and re-installed.  Every
+    output equals the single-request call and the oracle, and every cipher
+    request counts as a hit or a miss."""
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_tenant_requests(torch, 500, n_keys, 31 + n_keys)
+    log(f"key slots: {n_keys} keys, {slots} slots, {len(reqs)} requests")
+    with A.Engine(key_slots=slots, n_streams=2) as eng:
+        for r in reqs[:60]:
+            eng.wait(eng.submit(r[4]))
+        st1 = eng.stats()
+        for lo in range(60, len(reqs), 110):
+            ts = [eng.submit(r[4]) for r in reqs[lo:lo + 110]]
+            for t in ts:
+                eng.wait(t)
+        st = eng.stats()
+    assert st["key_hits"] + st["key_misses"] == len(reqs)
+    if n_keys <= slots:
+        # One at a time, each key misses once (its install), then hits.
+        assert st1["key_hits"] >= 60 - 2 * n_keys
+        assert st["key_hits"] > len(reqs) * 3 // 4
+    else:
+        # Uniform draws over more keys than slots: about slots / keys hit.
+        assert st["key_hits"] > len(reqs) // 8
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(n_keys))
+
+
+def test_without_key_slots_nothing_is_counted():
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_tenant_requests(torch, 50, 3, 5)
+    with A.Engine() as eng:
+        for t in [eng.submit(r[4]) for r in reqs]:
+            eng.wait(t)
+        st = eng.stats()
+    assert st["key_hits"] == 0 and st["key_misses"] == 0
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(5))
+
+
+@pytest.mark.parametrize("in_place", [False, True], ids=["out_of_place", "in_place"])
+def test_budget_counts_device_bytes(in_place):
+    """The admission weight of a cipher request is its buffers (input and
+    output, once when in place) plus its staged records; with one request in
+    flight the budget's high-water mark is exactly that."""
+    torch = torch_cuda()
+    A = lib()
+    n = 8 * MiB
+    buf = torch.zeros(2 * n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    s = A.aes_expand_key(bytes(range(16)))
+    out = buf.data_ptr() if in_place else buf.data_ptr() + n
+    overhead = A.lib.aes_engine_request_overhead()
+    assert overhead == 64 + 256
+    with A.Engine() as eng:
+        eng.wait(eng.submit(A.Request(s, bytes(12), 1, buf.data_ptr(), out, n)))
+        st = eng.stats()
+    assert st["budget_high_water"] == (1 if in_place else 2) * n + overhead
+    got = buf[n:].cpu().numpy() if not in_place else buf[:n].cpu().numpy()
+    ref = oracle.ctr(bytes(range(16)), bytes(12), 1, np.zeros(n, np.uint8))
+    assert np.array_equal(got[:4096], ref[:4096]) and np.array_equal(got[-4096:], ref[-4096:])
+
+
+def test_engines_do_not_grow_device_memory():
+    """Creating and destroying engines reuses the staging of retired
+    streams: 64 engines, each running a batch through the staged table (more
+    than 8 requests), a hash request and key slots, leave device memory
+    where it was (within a few MiB)."""
+    torch = torch_cuda()
+    A = lib()
+    src, dst, reqs, offs, lens = make_tenant_requests(torch, 24, 4, 71, sizes=(64 * KiB,), mix=(1.0,))
+    dig = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    def one_engine():
+        with A.Engine(key_slots=8, n_streams=2) as eng:
+            ts = [eng.submit(r[4]) for r in reqs]
+            ts.append(eng.submit(A.HashRequest(src, dig, 4096)))
+            for t in ts:
+                eng.wait(t)
+
+    for _ in range(4):          # the pools reach their steady size
+        one_engine()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    for i in range(64):
+        one_engine()
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    log(f"free device memory {free0 / MiB:.1f} -> {free1 / MiB:.1f} MiB after 64 engines")
+    assert free0 - free1 < 4 * MiB
+    check_alone_and_oracle(torch, src, dst, reqs, offs, lens, np.random.default_rng(72))

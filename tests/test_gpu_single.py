@@ -46,12 +46,13 @@ def gpu_crypt(key: bytes, nonce: bytes, ctr0: int, data: np.ndarray, cfg=None,
 TT_SHAPES = [dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w)
              for c, t in ((32, 4), (64, 2), (32, 2)) for b in (1, 2, 4) for w in (256, 1024)]
 BS_SHAPES = [dict(variant=2, wg_size=w) for w in (64, 256)]
-SHAPES = TT_SHAPES + BS_SHAPES
+VP_SHAPES = [dict(variant=3, wg_size=w) for w in (64, 256)]
+SHAPES = TT_SHAPES + BS_SHAPES + VP_SHAPES
 
 
 def shape_id(kw):
     short = {"lds_copies": "c", "lds_tables": "t", "blocks_per_lane": "b", "wg_size": "w"}
-    name = "tt" if kw["variant"] == 1 else "bs"
+    name = {1: "tt", 2: "bs", 3: "vp"}[kw["variant"]]
     return name + "".join(f"-{short[k]}{v}" for k, v in kw.items() if k != "variant")
 
 
@@ -65,13 +66,13 @@ def test_single_1mib_matches_oracle():
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("variant", [0, 2], ids=["default", "bs"])
+@pytest.mark.parametrize("variant", [0, 2, 3], ids=["default", "bs", "vp"])
 @pytest.mark.parametrize("bits", [128, 256])
 @pytest.mark.parametrize("size", W.SWEEP_SIZES + [W.BIG_SIZE])
 def test_sweep_full_size_digest(bits, size, variant):
-    """Every sweep size, in the default launch shape and in the bitsliced
-    kernel's, against the oracle-written digest (the configurations the
-    benchmark's sweep times)."""
+    """Every sweep size, in the default launch shape and in the bitsliced and
+    vector-permute kernels', against the oracle-written digest (the
+    configurations the benchmark's sweep times)."""
     key, nonce = W.sweep_key(bits)
     data = W.sweep_payload(size, bits)
     log(f"sweep AES-{bits} {size} B variant {variant}")
@@ -102,7 +103,7 @@ def test_launch_shapes_match_oracle(kw, klen, ctr0):
 LENGTHS = [1, 15, 16, 17, 31, 33, 1023, 4095, 4096, 4097, 65537, (1 << 20) + 15]
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["tt", "bs"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["tt", "bs", "vp"])
 @pytest.mark.parametrize("n", LENGTHS)
 def test_lengths(variant, n):
     g = np.random.default_rng(n)
@@ -112,7 +113,7 @@ def test_lengths(variant, n):
     assert np.array_equal(got, oracle.ctr(key, nonce, 5, data))
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["tt", "bs"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["tt", "bs", "vp"])
 @pytest.mark.parametrize("offs", [(1, 0), (0, 3), (7, 7), (15, 9), (4, 8)])
 def test_unaligned_buffers(variant, offs):
     g = np.random.default_rng(offs[0] * 16 + offs[1])
@@ -123,7 +124,7 @@ def test_unaligned_buffers(variant, offs):
     assert np.array_equal(got, oracle.ctr(key, nonce, 9, data))
 
 
-@pytest.mark.parametrize("variant", [1, 2], ids=["tt", "bs"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["tt", "bs", "vp"])
 def test_in_place(variant):
     torch = torch_cuda()
     g = np.random.default_rng(99)
@@ -137,7 +138,7 @@ def test_in_place(variant):
 
 
 @pytest.mark.parametrize("klen", [16, 32])
-@pytest.mark.parametrize("variant", [1, 2], ids=["tt", "bs"])
+@pytest.mark.parametrize("variant", [1, 2, 3], ids=["tt", "bs", "vp"])
 @pytest.mark.parametrize("ctr0", [0xFFFFFFFF, 0xFFFFFF00, 0xFFFFFFF0, 0x7FFFFF00, 0x80000013, 0xC0FFEE00])
 def test_counter_wrap(variant, ctr0, klen):
     """Counters that wrap mod 2^32, and counters at and above 2^31 (where a
@@ -252,3 +253,5 @@ def test_default_shapes_pick_the_lds_layout_by_size():
     assert shape(128, 8 * MiB, lds_tables=4)["lds_tables"] == 4
     s = shape(128, MiB, variant=2)
     assert (s["lds_copies"], s["lds_tables"]) == (0, 0), s
+    s = shape(128, MiB, variant=3, blocks_per_lane=4)
+    assert (s["variant"], s["lds_copies"], s["lds_tables"], s["blocks_per_lane"]) == (3, 0, 0, 1), s

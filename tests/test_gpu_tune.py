@@ -1,7 +1,9 @@
 """The autotuner and its cache (GPU).
 
 The autotuner times only candidates whose output digest equals the one the
-oracle wrote (tests/golden/ctr_digests.json) and exits non-zero otherwise.
+oracle wrote (tests/golden/ctr_digests.json, passed with --golden) and exits
+non-zero otherwise; batch candidates must reproduce the oracle's sampled
+keystream digest of the 4096-request workload.
 This test runs it on two sizes in a subprocess, then, in a fresh process
 pointed at the written cache (AESCTR_TUNE_CACHE), checks the round trip:
 aes_ctr_launch_shape returns each cached shape for its size, and
@@ -19,6 +21,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden", "ctr_digests.json")
 SIZES = [65536, 1048576]
 
 CHECK = r"""
@@ -31,7 +34,7 @@ gold = json.load(open("tests/golden/ctr_digests.json"))["sweep"]
 cus = torch.cuda.get_device_properties(0).multi_processor_count
 checked = 0
 for e in cache["entries"]:
-    if e["variant"] not in (1, 2):
+    if e["variant"] not in (1, 2, 3):
         continue
     size, bits = 1 << e["size_log2"], e["key_bits"]
     shape = A.launch_shape(bits, size, A.launch_cfg(variant=e["variant"]))
@@ -55,12 +58,12 @@ def test_autotune_writes_a_cache_the_library_uses(tmp_path):
     env = dict(os.environ)
     env.pop("AESCTR_TUNE_CACHE", None)
     r = subprocess.run([sys.executable, "-m", "paper_2607_02630_amd.autotune", "--sizes",
-                        ",".join(map(str, SIZES)), "--no-batch", "--out", str(out)],
+                        ",".join(map(str, SIZES)), "--no-batch", "--out", str(out), "--golden", GOLDEN],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
     cache = json.loads(out.read_text())
     have = {(e["variant"], e["key_bits"], e["size_log2"]) for e in cache["entries"]}
-    for v in (1, 2):
+    for v in (1, 2, 3):
         for bits in (128, 256):
             for size in SIZES:
                 assert (v, bits, size.bit_length() - 1) in have
@@ -68,4 +71,25 @@ def test_autotune_writes_a_cache_the_library_uses(tmp_path):
     r = subprocess.run([sys.executable, "-c", CHECK, str(out)], cwd=ROOT, env=env, capture_output=True,
                        text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
-    assert "checked 8" in r.stdout
+    assert "checked 12" in r.stdout
+
+
+def test_batch_tuner_checks_every_candidate(tmp_path):
+    """The batch-kernel search on the 4096-request workload: each candidate
+    runs on zero payloads and its sampled keystream must hash to the digest
+    the oracle wrote; the cache gets the winner's tiling constants, and a
+    batch call under that cache still reproduces the digest."""
+    out = tmp_path / "tune_cache.json"
+    env = dict(os.environ)
+    env.pop("AESCTR_TUNE_CACHE", None)
+    r = subprocess.run([sys.executable, "-m", "paper_2607_02630_amd.autotune", "--sizes", "4096",
+                        "--out", str(out), "--golden", GOLDEN], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    cache = json.loads(out.read_text())
+    batch = [e for e in cache["entries"] if e["variant"] == 10]
+    assert len(batch) == 1
+    e = batch[0]
+    assert e["tiles_per_cu"] in (8, 16, 32) and e["max_tile_bytes"] in (65536, 262144, 1 << 20)
+    assert e["bpl"] in (1, 2)
+    assert r.stdout.count('"batch"') == 18
