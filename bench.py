@@ -11,8 +11,10 @@ launches and the per-launch rate does not depend on --steps.  Buffers rotate
 over more than 512 MiB so the 256 MB Infinity Cache cannot serve repeats.
 The eager (one ctypes call per launch) rate is reported beside it.
 
-Prints ONE JSON line.  Extra legs (--sweep, --batch, --serve) add fields to
-that line; the CPU oracle leg (cpu_baseline) runs unless --no-cpu.
+Prints ONE JSON line.  Extra legs (the sweep with --sweep; the batch,
+serving, hash and asyncio legs unless --no-batch / --no-serve / --no-hash /
+--no-aio) add fields to that line; the CPU oracle leg (cpu_baseline) runs
+unless --no-cpu.
 """
 from __future__ import annotations
 
@@ -46,11 +48,12 @@ def parse():
                     help="launches per step, K (0 = enough for a replay of at least 20 ms)")
     ap.add_argument("--size", type=int, default=8 * MiB, help="bytes per buffer")
     ap.add_argument("--bits", type=int, default=128, choices=(128, 256))
-    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 T-table, 2 bitsliced")
+    ap.add_argument("--variant", type=int, default=0, help="0 auto, 1 T-table, 2 bitsliced, 3 vector permute")
     ap.add_argument("--sweep", action="store_true", help="also time 4 KiB..8 MiB + 256 MiB")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-request batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-hash", action="store_true", help="skip the batched SHA-256 leg")
+    ap.add_argument("--no-aio", action="store_true", help="skip the asyncio reroute leg")
     ap.add_argument("--serve-requests", type=int, default=100_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -294,7 +297,7 @@ VALU_PER_BLOCK_8MIB = {128: 347.0, 256: 467.0}
 def valu_roofline(args, gbs, cus, clk):
     """The T-table kernel's second ceiling at 8 MiB: VALU issue at the
     measured lane operations per block (its LDS-issue ceiling is `roofline`)."""
-    if args.variant == 2 or args.size != 8 * MiB:
+    if args.variant in (2, 3) or args.size != 8 * MiB:
         return {}
     v = VALU_PER_BLOCK_8MIB[args.bits]
     peak = cus * 64 * clk / v * 16 / 1e9
@@ -526,6 +529,8 @@ def main():
         result["serving"] = serve_leg(torch, A, W, args.serve_requests)
     if not args.no_hash:
         result["hash"] = hash_leg(torch, A, W, with_cpu=not args.no_cpu)
+    if not args.no_aio:
+        result["aio"] = aio_leg(torch)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(W, args.size, args.bits, args.cpu_seconds)
@@ -562,7 +567,7 @@ def run_sweep(torch, A, W, args):
         key, nonce = W.sweep_key(bits)
         sched = A.aes_expand_key(key)
         for size in W.SWEEP_SIZES + [W.BIG_SIZE]:
-            for variant in (1, 2):
+            for variant in (1, 2, 3):
                 cfg = A.launch_cfg(variant=variant)
                 payload, ins, outs = make_buffers(torch, W, size, bits)
                 # Parity gate on this exact (variant, key size, size) before it is timed.
@@ -579,8 +584,9 @@ def run_sweep(torch, A, W, args):
                        "single_launch_us": round(lat, 2), "parity_vs_oracle_digest": True}
                 if variant == 1:
                     row["end_to_end_pinned_gbs"] = round(end_to_end_gbs(torch, A, sched, nonce, payload)[0], 3)
-                out[f"aes{bits}/{'tt' if variant == 1 else 'bs'}/{size}"] = row
-                log(f"sweep {bits} {'tt' if variant == 1 else 'bs'} {size}: {row}")
+                name = {1: "tt", 2: "bs", 3: "vp"}[variant]
+                out[f"aes{bits}/{name}/{size}"] = row
+                log(f"sweep {bits} {name} {size}: {row}")
                 del ins, outs
                 torch.cuda.empty_cache()
     return out
@@ -808,6 +814,72 @@ def serve_pinned(torch, A, W, g, n_req, npool=2000, budget=4 << 30):
     return out
 
 
+def tenant_key_points(torch, A, W, src, dst, lens, offs, rate, n_req, n_keys=64, slots=64):
+    """The serving mix with keys that repeat: every request uses one of 64
+    tenant keys (own nonce and counter).  One engine keeps the schedules in
+    64 resident key slots, another carries every key inline; both replay the
+    same open-loop schedules at 50% and 90% of the saturation rate."""
+    import numpy as np
+    from paper_2607_02630_amd import loadgen
+    g = np.random.default_rng(W.seed_for(6))
+    dst = torch.zeros_like(dst)         # its own outputs
+    torch.cuda.synchronize()
+    scheds = [A.aes_expand_key(g.bytes(16)) for _ in range(n_keys)]
+    which = g.integers(0, n_keys, size=len(lens))
+    objs = [A.Request(scheds[int(k)], g.bytes(12), int(g.integers(0, 1 << 32)), src.data_ptr() + int(o),
+                      dst.data_ptr() + int(o), int(L)) for k, o, L in zip(which, offs, lens)]
+    pool = A.make_desc_array(objs)
+    out = {"tenant_keys": n_keys, "key_slots": slots, "requests_per_point": n_req}
+    for name, ks in (("resident", slots), ("inline", 0)):
+        with A.Engine(n_streams=2, key_slots=ks) as eng:
+            loadgen.run_engine(eng, pool, np.zeros(min(20000, n_req)))
+            pts = []
+            for frac in (0.5, 0.9):
+                arr = W.serving_trace(n_req, frac * rate)[0]
+                e = loadgen.run_engine(eng, pool, arr)
+                st = eng.stats()
+                hits, misses = st["key_hits"], st["key_misses"]
+                pts.append({"offered_frac": frac, "offered_rps": round(frac * rate, 1),
+                            "engine": {k: round(v, 3) for k, v in e.items()},
+                            "key_hits": hits, "key_misses": misses,
+                            "hit_rate": round(hits / max(1, hits + misses), 4)})
+                log(f"tenant keys, {name}, {frac:.0%}: p50 {e['p50_us']:.0f} p99 {e['p99_us']:.0f} us, "
+                    f"key hits {hits} / {hits + misses}")
+            out[name] = pts
+    # Outputs of the tenant-key pool equal the single-request call.
+    torch.cuda.synchronize()
+    alone = torch.zeros_like(dst)
+    for o in objs:
+        A.aes_ctr_crypt(o.sched, o.nonce, o.ctr0, o.x, alone.data_ptr() + (o.out - dst.data_ptr()),
+                        length=o.length)
+    torch.cuda.synchronize()
+    out["same_alone_and_in_the_mix"] = bool(torch.equal(alone, dst))
+    if not out["same_alone_and_in_the_mix"]:
+        raise SystemExit("tenant-key serving outputs differ from the single-request outputs")
+    del alone, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def aio_leg(torch, sizes=(4096, MiB, 8 * MiB), clients=50, seconds=1.0):
+    """The shape of the paper's Appendix A, Table 2 on this GPU: one asyncio
+    event loop serving 50 closed-loop clients, each request doing a little
+    CPU work plus one AES-CTR offload of the block size, served
+    synchronously (the offload blocks the loop) and rerouted (submit, await
+    the engine's completion, resume), in requests per second."""
+    import asyncio
+    from paper_2607_02630_amd import aio
+    rows = []
+    for size in sizes:
+        sync = asyncio.run(aio._serve("sync", size, clients, seconds, torch))
+        asy = asyncio.run(aio._serve("async", size, clients, seconds, torch))
+        rows.append({"block_bytes": size, "sync_rps": round(sync, 1), "async_rps": round(asy, 1),
+                     "speedup": round(asy / sync, 2)})
+        log(f"aio {size} B: sync {sync:.0f} req/s, rerouted {asy:.0f} req/s")
+    torch.cuda.empty_cache()
+    return {"clients": clients, "seconds_per_point": seconds, "rows": rows}
+
+
 def serve_leg(torch, A, W, n_req=100_000, budget=4 << 30):
     """Open-loop Poisson arrivals at 10/50/90% of the engine's measured
     saturation rate on the serving mix (70% 64 KiB / 25% 1 MiB / 5% 8 MiB,
@@ -851,6 +923,24 @@ def serve_leg(torch, A, W, n_req=100_000, budget=4 << 30):
                 f" sync p99 {s['p99_us']:.0f} us {s['gbps']:.1f} GB/s")
         out["points"] = points
         out["engine_stats"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in eng.stats().items()}
+        # Both paths below the synchronous path's own knee: offered loads of
+        # 10/50/90% of the rate the synchronous path sustains.
+        m = min(n_req, 20000)
+        sync_sat = loadgen.run_sync(pool, np.zeros(m), torch.cuda.current_stream().cuda_stream)
+        srate = sync_sat["achieved_rps"]
+        sync_points = []
+        for frac in (0.1, 0.5, 0.9):
+            arr = W.serving_trace(m, frac * srate)[0]
+            e = loadgen.run_engine(eng, pool, arr)
+            s = loadgen.run_sync(pool, arr, torch.cuda.current_stream().cuda_stream)
+            sync_points.append({"offered_frac_of_sync_saturation": frac, "offered_rps": round(frac * srate, 1),
+                                "engine": {k: round(v, 3) for k, v in e.items()},
+                                "sync_per_request": {k: round(v, 3) for k, v in s.items()}})
+            log(f"serving at {frac:.0%} of sync saturation ({frac * srate:.0f} req/s): engine p50 "
+                f"{e['p50_us']:.0f} p99 {e['p99_us']:.0f} us; sync p50 {s['p50_us']:.0f} p99 {s['p99_us']:.0f} us")
+        out["sync_saturation"] = {k: round(v, 3) for k, v in sync_sat.items()}
+        out["sync_points"] = sync_points
+    out["tenant_keys"] = tenant_key_points(torch, A, W, src, dst, lens, offs, rate, min(n_req, 50000))
     out["pinned_host"] = serve_pinned(torch, A, W, g, min(n_req, 20000))
     # Results are the same in the mix as alone: every pool entry's output.
     torch.cuda.synchronize()
