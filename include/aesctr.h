@@ -56,7 +56,8 @@ typedef enum {
     AES_ETIMEDOUT = -7,   /* engine: aes_wait deadline passed */
     AES_EOVERLAP = -8,    /* input and output partially overlap */
     AES_ECLOSED = -9,     /* engine is shutting down */
-    AES_ECANCELED = -10   /* engine: request dropped at shutdown */
+    AES_ECANCELED = -10,  /* engine: request dropped at shutdown */
+    AES_ETOOBIG = -11     /* more requests than a fixed-size table holds */
 } aes_status_t;
 
 /* Human-readable name of a status value (static string, never NULL). */
@@ -208,6 +209,23 @@ typedef struct {
 
 int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n,
                             const aes_batch_cfg_t *cfg, void *stream);
+
+/* aes_ctr_crypt_batch for callers that cannot allocate (code that must not
+ * call hipMalloc or create library state at run time: tight serving loops,
+ * harnesses that forbid allocation).  It allocates nothing, host or device:
+ * the descriptor table lives in a fixed device array of the library's, 1.25
+ * MiB per GPU (held until the process ends), and is built on the calling
+ * thread's stack and copied in with hipMemcpyAsync from that pageable memory
+ * on `stream`, then the same persistent batch kernel runs over it.  Every
+ * request's key travels inline.  Output equals aes_ctr_crypt_batch's (and so
+ * aes_ctr_crypt's on each request alone).
+ * Limits: at most 4096 requests per call (more: AES_ETOOBIG, before any
+ * device work).  All calls on one GPU share that array: calls that overlap
+ * on one GPU (another thread, another stream) race and must be serialised by
+ * the caller; a call may be made again as soon as the previous one returned
+ * on the same stream.  Not for a stream under graph capture (AES_EINVAL).
+ * Errors: as aes_ctr_crypt_batch, plus AES_ETOOBIG. */
+int aes_ctr_crypt_batch_noalloc(const aes_ctr_desc_t *desc, size_t n, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Engine: submit -> (caller suspends) -> poll / wait -> resume            */

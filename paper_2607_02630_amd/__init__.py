@@ -231,6 +231,13 @@ def aes_ctr_crypt_batch(reqs, stream=None, cfg: aes_batch_cfg_t | None = None, d
     _check(rc, "aes_ctr_crypt_batch")
 
 
+def aes_ctr_crypt_batch_noalloc(reqs, stream=None, descs=None) -> None:
+    """aes_ctr_crypt_batch without any allocation (at most 4096 requests per
+    call; calls that overlap on one GPU race: see include/aesctr.h)."""
+    arr = descs if descs is not None else make_desc_array(reqs)
+    _check(lib.aes_ctr_crypt_batch_noalloc(arr, len(reqs), _stream(stream)), "aes_ctr_crypt_batch_noalloc")
+
+
 def batch_cfg(tile_bytes: int = 0, wg_size: int = 0, grid: int = 0, blocks_per_lane: int = 0,
               use_graph: int = 1) -> aes_batch_cfg_t:
     """Launch shape for aes_ctr_crypt_batch (aes_batch_cfg_t); zero fields keep

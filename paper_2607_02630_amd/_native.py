@@ -23,6 +23,7 @@ AES_ETIMEDOUT = -7
 AES_EOVERLAP = -8
 AES_ECLOSED = -9
 AES_ECANCELED = -10
+AES_ETOOBIG = -11
 AES_FLAG_SHA256 = 1
 
 AES_VARIANT_AUTO = 0
@@ -93,6 +94,8 @@ SIGNATURES = {
                                            ctypes.c_void_p]),
     "aes_ctr_crypt_batch_cfg": (ctypes.c_int, [ctypes.POINTER(aes_ctr_desc_t), ctypes.c_size_t,
                                                ctypes.POINTER(aes_batch_cfg_t), ctypes.c_void_p]),
+    "aes_ctr_crypt_batch_noalloc": (ctypes.c_int, [ctypes.POINTER(aes_ctr_desc_t), ctypes.c_size_t,
+                                                   ctypes.c_void_p]),
     "aes_engine_create": (ctypes.c_int, [ctypes.POINTER(aes_engine_cfg_t),
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "aes_engine_destroy": (ctypes.c_int, [ctypes.c_void_p]),

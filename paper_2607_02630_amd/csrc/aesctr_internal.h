@@ -226,6 +226,7 @@ int check_desc(const aes_ctr_desc_t &d);
 uint64_t batch_tile_bytes(uint64_t batch_bytes, int num_cus);
 int batch_blocks_per_lane();
 void make_batch_record(const aes_ctr_desc_t &d, RequestRec *o);
+void make_batch_desc(const aes_ctr_desc_t &d, BatchDesc *o, KeyRec *k);
 int launch_spec(int device, hipStream_t st, const LaunchSpec &spec, int tile_bytes, int grid, int bpl,
                 bool use_graph, bool allow_small);
 // Completes a staged table of n requests at buf (descriptors, keys and

@@ -190,6 +190,7 @@ extern "C" const char *aes_strerror(int status)
     case AES_EOVERLAP: return "AES_EOVERLAP: input and output partially overlap";
     case AES_ECLOSED: return "AES_ECLOSED: engine is shutting down";
     case AES_ECANCELED: return "AES_ECANCELED: request canceled";
+    case AES_ETOOBIG: return "AES_ETOOBIG: more requests than the fixed table holds";
     default: return "unknown aes status";
     }
 }

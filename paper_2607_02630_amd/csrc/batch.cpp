@@ -365,10 +365,8 @@ int batch_blocks_per_lane()
     return tune_lookup_batch(&te) && (te.bpl == 1 || te.bpl == 2) ? te.bpl : 2;
 }
 
-namespace {
-
 // Descriptor (key field left 0) and round keys of one validated request.
-void make_record(const aes_ctr_desc_t &d, BatchDesc *o, KeyRec *k)
+void make_batch_desc(const aes_ctr_desc_t &d, BatchDesc *o, KeyRec *k)
 {
     KeyMaterial km;
     make_key_material(*d.sched, d.nonce, &km);
@@ -385,11 +383,9 @@ void make_record(const aes_ctr_desc_t &d, BatchDesc *o, KeyRec *k)
     memcpy(k->rk, km.rk, sizeof(km.rk));
 }
 
-}  // namespace
-
 void make_batch_record(const aes_ctr_desc_t &d, RequestRec *o)
 {
-    make_record(d, &o->d, &o->key);
+    make_batch_desc(d, &o->d, &o->key);
 }
 
 int check_desc(const aes_ctr_desc_t &d)
@@ -476,7 +472,7 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
         BatchDesc descs[kSmallBatch];
         KeyRec keys[kSmallBatch];
         for (size_t i = 0; i < n; ++i) {
-            make_record(desc[i], &descs[i], &keys[i]);
+            make_batch_desc(desc[i], &descs[i], &keys[i]);
             descs[i].key = static_cast<uint32_t>(i);
         }
         LaunchSpec spec;
@@ -506,7 +502,7 @@ extern "C" int aes_ctr_crypt_batch_cfg(const aes_ctr_desc_t *desc, size_t n, con
         KeyRec *keys = reinterpret_cast<KeyRec *>(buf + batch_keys_off(m));
         HostPool::get().parallel_for(m, kRecordGrain, [&](size_t, size_t b, size_t e) {
             for (size_t i = b; i < e; ++i) {
-                make_record(desc[first + i], out + i, keys + i);
+                make_batch_desc(desc[first + i], out + i, keys + i);
                 out[i].key = static_cast<uint32_t>(i);
             }
         });
