@@ -292,6 +292,11 @@ def measured_traffic(bits, size, variant):
 # / blocks (two-table layout, 512-thread workgroups, two per CU, each wave
 # computing its first chunk's group constants).
 VALU_PER_BLOCK_8MIB = {128: 347.0, 256: 467.0}
+# VALU lane operations per block of the kernels without LDS tables: the
+# bitsliced kernel (rocprofv3 SQ_INSTS_VALU at 256 MiB) and the
+# vector-permute kernel (instructions per keystream block in the built code).
+VALU_PER_BLOCK_BS = {128: 814, 256: 1096}
+VALU_PER_BLOCK_VP = {128: 2311, 256: 3307}
 
 
 def valu_roofline(args, gbs, cus, clk):
@@ -459,8 +464,8 @@ def main():
     # has no lookups and is bound by VALU issue (64 lane-ops per clock per CU,
     # at its own instruction count per block).
     clk = 2.4e9
-    if args.variant == 2:
-        valu_per_block = 814 if nr == 10 else 814 * 14 // 10
+    if args.variant in (2, 3):
+        valu_per_block = (VALU_PER_BLOCK_BS if args.variant == 2 else VALU_PER_BLOCK_VP)[args.bits]
         alu_peak_gbs = cus * 64 * clk / valu_per_block * 16 / 1e9
         alu_note = f"payload GB/s vs the VALU-issue ceiling of {valu_per_block} ops per block"
     else:

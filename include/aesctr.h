@@ -121,11 +121,17 @@ typedef enum {
  *                    128 KiB) or 2 (T0 and T2, T1 and T3 by rotation: 32
  *                    copies in 64 KiB, or 64 copies in 128 KiB).  64 copies
  *                    imply 2 tables; 64 copies of 4 tables is AES_EINVAL.
- *   wave_groups      set by aes_ctr_launch_shape, ignored on input: 1 when
- *                    every wave computes the counter-group constants of its
- *                    first chunk itself (2 tables of 32 copies, 2 blocks per
- *                    lane, <= 512 threads and at least two workgroups per
- *                    CU), 0 when wave 0 computes them for its workgroup. */
+ *   wave_groups      how the T-table kernel's first chunk gets rounds 1-2
+ *                    (counter-mode caching shares them across groups of 256
+ *                    counters).  Input: 0 = the shape rule's choice, 1 =
+ *                    every wave computes its own group constants (2 tables
+ *                    of 32 copies, 1-2 blocks per lane, <= 512 threads), 2 =
+ *                    rounds 1-2 in full for the first chunk, no group
+ *                    constants (1-2 blocks per lane, <= 512 threads), 3 =
+ *                    wave 0 computes them for its workgroup; a mode the
+ *                    shape is not built for is AES_EINVAL.  Output (from
+ *                    aes_ctr_launch_shape): the mode used, 1, 2, or 0 for
+ *                    wave 0. */
 typedef struct {
     int32_t variant;
     int32_t blocks_per_lane;

@@ -88,15 +88,18 @@ def _nonce(nonce: bytes) -> bytes:
 
 
 def launch_cfg(variant: int = 0, blocks_per_lane: int = 0, wg_size: int = 0, grid: int = 0,
-               lds_copies: int = 0, lds_tables: int = 0) -> aes_launch_cfg_t:
+               lds_copies: int = 0, lds_tables: int = 0, wave_groups: int = 0) -> aes_launch_cfg_t:
     """Launch shape for aes_ctr_crypt (aes_launch_cfg_t); zero fields keep the
     default.  variant: AES_VARIANT_TTABLE (1), AES_VARIANT_BITSLICE (2) or
     AES_VARIANT_VPERM (3);
     lds_copies / lds_tables: the T-table layout in LDS, 32 or 64 copies of 4
-    or 2 tables (64 copies only with 2 tables)."""
+    or 2 tables (64 copies only with 2 tables); wave_groups: the T-table
+    kernel's first-chunk mode (0 rule, 1 per-wave group constants, 2 rounds
+    1-2 in full, 3 wave 0 for the workgroup)."""
     c = aes_launch_cfg_t()
     c.variant, c.blocks_per_lane, c.wg_size, c.grid, c.lds_copies, c.lds_tables = (
         variant, blocks_per_lane, wg_size, grid, lds_copies, lds_tables)
+    c.wave_groups = wave_groups
     return c
 
 

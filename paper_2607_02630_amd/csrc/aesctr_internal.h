@@ -38,8 +38,22 @@ struct Shape {
     int grid;           // workgroups
     int copies;         // T-table replication (32 or 64 copies per table)
     int tables;         // T-tables in LDS: 4 (T0..T3) or 2 (T0, T2)
-    bool wave_groups;   // each wave computes its first chunk's group constants
+    int wave_groups;    // first chunk's rounds 1-2 (T-table kernel): kFirstWave0,
+                        // kFirstPerWave or kFirstFull
 };
+
+// First-chunk modes of the T-table kernel (Shape::wave_groups, and the
+// wave_groups field of aes_launch_cfg_t on output).
+enum : int { kFirstWave0 = 0, kFirstPerWave = 1, kFirstFull = 2 };
+// Whether a shape is built with first-chunk mode m.
+inline bool first_chunk_mode_ok(int m, int copies, int tables, int bpl, int wg)
+{
+    if (m == kFirstWave0)
+        return true;
+    if (bpl > 2 || wg > 512)
+        return false;
+    return m == kFirstFull || (m == kFirstPerWave && copies == 32 && tables == 2);
+}
 
 // Arguments of the single-buffer kernels (passed by value in the kernarg
 // segment; the round keys become scalar registers).

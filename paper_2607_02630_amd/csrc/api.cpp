@@ -94,6 +94,7 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
 {
     Shape sh{};
     sh.variant = variant == AES_VARIANT_AUTO ? AES_VARIANT_TTABLE : variant;
+    sh.wave_groups = -1;    // first-chunk mode: the rule's (resolve_shape)
     TuneEntry te;
     if (tune_lookup(sh.variant, key_bits, len, &te)) {
         sh.bpl = te.bpl;
@@ -101,6 +102,9 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         sh.copies = te.copies;
         sh.tables = te.tables ? te.tables : (te.copies == 64 ? 2 : 4);
         sh.grid = te.grid_per_cu * di.num_cus;
+        if (te.first >= kFirstWave0 && te.first <= kFirstFull &&
+            first_chunk_mode_ok(te.first, sh.copies, sh.tables, sh.bpl, sh.wg))
+            sh.wave_groups = te.first;
     } else if (sh.variant == AES_VARIANT_TTABLE) {
         // The LDS holds only T0 and T2 (32 copies, 64 KiB): half the table
         // fill of four tables, for about 15% more VALU work per block, and
@@ -214,6 +218,8 @@ int check_cfg(const aes_launch_cfg_t *cfg, int *variant)
             return AES_EINVAL;
         if (cfg->lds_copies == 64 && cfg->lds_tables == 4)   // 256 KiB: more than a CU's LDS
             return AES_EINVAL;
+        if (cfg->wave_groups < 0 || cfg->wave_groups > 3)
+            return AES_EINVAL;
     }
     return AES_OK;
 }
@@ -244,12 +250,21 @@ Shape resolve_shape(int variant, int key_bits, uint64_t len, const aes_launch_cf
     if (sh.variant == AES_VARIANT_VPERM)
         sh.bpl = 1;     // one block per lane, whatever cfg asks
     clamp_grid(&sh, len);
-    // Per-wave first-chunk group constants pay off when two workgroups with
-    // the 64 KiB image share each CU (8 MiB AES-128: 7.64-7.69 against
-    // 7.74-7.78 us); with one workgroup per CU they cost more than wave 0
-    // computing them for all (4 MiB: 5.39 against 5.30 us).
-    sh.wave_groups = sh.variant == AES_VARIANT_TTABLE && sh.copies == 32 && sh.tables == 2 && sh.bpl == 2 &&
-                     sh.wg <= 512 && sh.grid >= 2 * di.num_cus;
+    // First-chunk mode of the T-table kernel.  Per-wave first-chunk group
+    // constants pay off when two workgroups with the 64 KiB image share each
+    // CU (8 MiB AES-128: 7.64-7.69 against 7.74-7.78 us); with one workgroup
+    // per CU they cost more than wave 0 computing them for all (4 MiB: 5.39
+    // against 5.30 us).
+    const int tuned = sh.wave_groups;
+    sh.wave_groups = kFirstWave0;
+    if (sh.variant == AES_VARIANT_TTABLE) {
+        if (cfg && cfg->wave_groups)
+            sh.wave_groups = cfg->wave_groups == 3 ? kFirstWave0 : cfg->wave_groups;
+        else if (tuned >= 0 && first_chunk_mode_ok(tuned, sh.copies, sh.tables, sh.bpl, sh.wg))
+            sh.wave_groups = tuned;
+        else if (sh.copies == 32 && sh.tables == 2 && sh.bpl == 2 && sh.wg <= 512 && sh.grid >= 2 * di.num_cus)
+            sh.wave_groups = kFirstPerWave;
+    }
     return sh;
 }
 
@@ -274,7 +289,10 @@ extern "C" int aes_ctr_launch_shape(int key_bits, size_t len, const aes_launch_c
     out->grid = sh.grid;
     out->lds_copies = sh.copies;
     out->lds_tables = sh.tables;
-    out->wave_groups = sh.wave_groups ? 1 : 0;
+    if (sh.variant == AES_VARIANT_TTABLE &&
+        !first_chunk_mode_ok(sh.wave_groups, sh.copies, sh.tables, sh.bpl, sh.wg))
+        return AES_EINVAL;
+    out->wave_groups = sh.wave_groups;
     return AES_OK;
 }
 

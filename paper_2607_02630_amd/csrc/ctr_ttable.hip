@@ -52,7 +52,9 @@ __device__ __forceinline__ void prefetch(const u32x4 *src, uint64_t start, uint3
     }
 }
 
-template <int NR, int LAYOUT, int BPL, bool ALIGNED>
+// FULL: rounds 1-2 of every block in full (no group constants); otherwise
+// round 2 from the wave's group constants w.
+template <int NR, int LAYOUT, int BPL, bool ALIGNED, bool FULL = false>
 __device__ __forceinline__ void chunk_step(const TTable<LAYOUT> &tt, const CtrArgs &a, const uint32_t *krot,
                                            uint64_t start, uint64_t chunk, uint32_t wave, uint32_t lane,
                                            uint64_t nfull, const WaveGroups &w, const u32x4 (&d)[BPL])
@@ -61,7 +63,10 @@ __device__ __forceinline__ void chunk_step(const TTable<LAYOUT> &tt, const CtrAr
 #pragma unroll
     for (int b = 0; b < BPL; ++b)
         ctr[b] = a.ctr0 + static_cast<uint32_t>(block_of<BPL>(start, wave, lane, b));
-    keystream_wave<NR, LAYOUT, BPL>(tt, a, krot, ctr, w, ks);
+    if constexpr (FULL)
+        keystream<NR, LAYOUT, BPL>(tt, a, krot, ctr, ks);
+    else
+        keystream_wave<NR, LAYOUT, BPL>(tt, a, krot, ctr, w, ks);
     if (start + chunk <= nfull) {
 #pragma unroll
         for (int b = 0; b < BPL; ++b)
@@ -84,10 +89,17 @@ __device__ __forceinline__ uint32_t first_ctr(const CtrArgs &a, uint64_t start, 
     return a.ctr0 + static_cast<uint32_t>(start + 64u * wave * BPL);
 }
 
-template <int NR, int LAYOUT, int BPL, int WG, bool ALIGNED, bool WAVEG>
+// How the first chunk gets its rounds 1-2 (FIRST): kFirstWave0 -- wave 0
+// computes the group constants of the workgroup's chunk from the LDS tables
+// and the waves pick theirs up after a second barrier; kFirstPerWave -- each
+// wave computes its own two groups' constants (four lanes per group);
+// kFirstFull -- the first chunk runs rounds 1-2 in full (15 more lookups
+// per block, no group constants and no second barrier).  Later chunks
+// compute theirs on the scalar unit.
+template <int NR, int LAYOUT, int BPL, int WG, bool ALIGNED, int FIRST>
 __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
 {
-    static_assert(!WAVEG || BPL == 2, "per-wave group constants are built for two blocks per lane");
+    static_assert(FIRST == kFirstWave0 || BPL <= 2, "the other first-chunk modes are built for 1-2 blocks per lane");
     __shared__ uint32_t lds[layout_lds_words(LAYOUT)];
 
     const uint64_t nfull = a.len >> 4;
@@ -116,15 +128,11 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     const uint32_t k = LAYOUT == kLayout2x64 ? lane : (lane & 31);
     TTable<LAYOUT> tt{reinterpret_cast<const char *>(lds), 4 * k, 4 * k | 0x10000u};
 
-    // Group constants of the first chunk, from the LDS tables.  Either each
-    // wave computes its own (WAVEG: four lanes per group), or wave 0 computes
-    // every group the workgroup's chunk touches (one lane each) and the
-    // waves pick theirs up after a second barrier.  Later chunks compute
-    // theirs on the scalar unit while other waves keep the pipes busy.
-    WaveGroups w;
-    if constexpr (WAVEG) {
+    // Group constants of the first chunk, from the LDS tables (see FIRST).
+    WaveGroups w{};
+    if constexpr (FIRST == kFirstPerWave) {
         w = wave_groups_lds<LAYOUT, BPL>(tt, a, first_ctr<BPL>(a, start, wave), lane);
-    } else {
+    } else if constexpr (FIRST == kFirstWave0) {
         static_assert(WG * BPL <= 4096, "a chunk must span at most kChunkGroups groups");
         __shared__ u32x4 s_groups[kChunkGroups];
         const uint32_t chunk_first = a.ctr0 + static_cast<uint32_t>(start);
@@ -164,7 +172,7 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     u32x4 e[BPL];
     if (start < nfull) {
         prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, e);
-        chunk_step<NR, LAYOUT, BPL, ALIGNED>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
+        chunk_step<NR, LAYOUT, BPL, ALIGNED, FIRST == kFirstFull>(tt, a, krot, start, chunk, wave, lane, nfull, w, d);
         start += step;
         while (start < nfull) {
             prefetch<ALIGNED, BPL>(src, start + step, wave, lane, nfull, last, d);
@@ -192,28 +200,36 @@ __global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
     }
 }
 
-template <int NR, int LAYOUT, int BPL, int WG, bool WAVEG>
+template <int NR, int LAYOUT, int BPL, int WG, int FIRST>
 int launch_g(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
     (void)hipGetLastError();   // not ours: left by earlier calls
     if (aligned)
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true, WAVEG>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true, FIRST>), dim3(sh.grid), dim3(WG), 0, st, a);
     else
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, false, WAVEG>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, false, FIRST>), dim3(sh.grid), dim3(WG), 0, st,
+                           a);
     return launch_status();
 }
 
-// Per-wave group constants are built only where the shape rule uses them:
-// two tables x 32 copies, two blocks per lane, up to 512 threads.
+// The per-wave and full first-chunk modes are built only for the shapes that
+// can use them (first_chunk_mode_ok): two tables x 32 copies for per-wave
+// constants, 1-2 blocks per lane, up to 512 threads.
 template <int NR, int LAYOUT, int BPL, int WG>
 int launch_w(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
-    if constexpr (LAYOUT == kLayout2x32 && BPL == 2 && WG <= 512) {
-        if (sh.wave_groups)
-            return launch_g<NR, LAYOUT, BPL, WG, true>(a, sh, st);
+    if constexpr (BPL <= 2 && WG <= 512) {
+        if constexpr (LAYOUT == kLayout2x32) {
+            if (sh.wave_groups == kFirstPerWave)
+                return launch_g<NR, LAYOUT, BPL, WG, kFirstPerWave>(a, sh, st);
+        }
+        if (sh.wave_groups == kFirstFull)
+            return launch_g<NR, LAYOUT, BPL, WG, kFirstFull>(a, sh, st);
     }
-    return launch_g<NR, LAYOUT, BPL, WG, false>(a, sh, st);
+    if (sh.wave_groups != kFirstWave0)
+        return AES_EINVAL;
+    return launch_g<NR, LAYOUT, BPL, WG, kFirstWave0>(a, sh, st);
 }
 
 template <int NR, int LAYOUT, int BPL>

@@ -60,6 +60,7 @@ void parse(const std::string &text)
             else if (name == "grid_per_cu") e.grid_per_cu = static_cast<int>(v);
             else if (name == "copies") e.copies = static_cast<int>(v);
             else if (name == "tables") e.tables = static_cast<int>(v);
+            else if (name == "first") e.first = static_cast<int>(v);
             else if (name == "tiles_per_cu") e.tiles_per_cu = static_cast<int>(v);
             else if (name == "max_tile_bytes") e.max_tile_bytes = static_cast<int>(v);
             q = colon + 1;

@@ -5,7 +5,8 @@
 // shared library.  Format:
 //   {"entries": [{"variant": 1, "key_bits": 128, "size_log2": 23, "bpl": 2,
 //                 "wg": 1024, "grid_per_cu": 1, "copies": 32, "tables": 2}, ...]}
-// ("tables" may be absent: then 2 with 64 copies, 4 with 32.)
+// ("tables" may be absent: then 2 with 64 copies, 4 with 32; "first", the
+// T-table kernel's first-chunk mode, may be absent: then the shape rule's.)
 // The batch kernel's entry has "variant": 10 and carries "tiles_per_cu" and
 // "max_tile_bytes" (the tile sizing rule's constants) and "bpl".
 // A lookup takes the entry of the same variant and key size whose size_log2
@@ -20,6 +21,7 @@ struct TuneEntry {
     int variant = 0, key_bits = 0, size_log2 = 0;
     int bpl = 0, wg = 0, grid_per_cu = 0, copies = 0, tables = 0;
     int tiles_per_cu = 0, max_tile_bytes = 0;
+    int first = -1;     // T-table first-chunk mode (Shape::wave_groups), -1 = not given
 };
 
 bool tune_lookup(int variant, int key_bits, uint64_t len, TuneEntry *out);

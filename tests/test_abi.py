@@ -96,7 +96,8 @@ def test_validation_before_device():
 def test_launch_cfg_validation():
     s = A.aes_expand_key(bytes(16))
     for kw in (dict(variant=4), dict(blocks_per_lane=3), dict(wg_size=100), dict(wg_size=2048),
-               dict(grid=-1), dict(lds_copies=16), dict(lds_tables=3), dict(lds_copies=64, lds_tables=4)):
+               dict(grid=-1), dict(lds_copies=16), dict(lds_tables=3), dict(lds_copies=64, lds_tables=4),
+               dict(wave_groups=4), dict(wave_groups=-1)):
         cfg = A.launch_cfg(**kw)
         rc = A.lib.aes_ctr_crypt_cfg(ctypes.byref(s), bytes(12), 1, 0x1000, 0x2000, 16,
                                      ctypes.byref(cfg), None)

@@ -45,13 +45,18 @@ def gpu_crypt(key: bytes, nonce: bytes, ctr0: int, data: np.ndarray, cfg=None,
 # Every LDS layout (copies, tables): four tables x 32, two x 64, two x 32.
 TT_SHAPES = [dict(variant=1, lds_copies=c, lds_tables=t, blocks_per_lane=b, wg_size=w)
              for c, t in ((32, 4), (64, 2), (32, 2)) for b in (1, 2, 4) for w in (256, 1024)]
+# The first-chunk modes (1 per-wave group constants, 2 rounds 1-2 in full,
+# 3 wave 0 for the workgroup) on the shapes built with them.
+FIRST_SHAPES = ([dict(variant=1, lds_copies=32, lds_tables=2, blocks_per_lane=b, wg_size=w, wave_groups=m)
+                 for b in (1, 2) for w in (256, 512) for m in (1, 2, 3)]
+                + [dict(variant=1, lds_copies=32, lds_tables=4, blocks_per_lane=1, wg_size=256, wave_groups=2)])
 BS_SHAPES = [dict(variant=2, wg_size=w) for w in (64, 256)]
 VP_SHAPES = [dict(variant=3, wg_size=w) for w in (64, 256)]
-SHAPES = TT_SHAPES + BS_SHAPES + VP_SHAPES
+SHAPES = TT_SHAPES + FIRST_SHAPES + BS_SHAPES + VP_SHAPES
 
 
 def shape_id(kw):
-    short = {"lds_copies": "c", "lds_tables": "t", "blocks_per_lane": "b", "wg_size": "w"}
+    short = {"lds_copies": "c", "lds_tables": "t", "blocks_per_lane": "b", "wg_size": "w", "wave_groups": "g"}
     name = {1: "tt", 2: "bs", 3: "vp"}[kw["variant"]]
     return name + "".join(f"-{short[k]}{v}" for k, v in kw.items() if k != "variant")
 
@@ -216,42 +221,77 @@ def test_overlap_rejected_on_device():
     assert rc == -8
 
 
-def test_default_shapes_pick_the_lds_layout_by_size():
-    """Without a tune cache: two T-tables (64 KiB of LDS) at every size, one
-    workgroup per CU up to 4 MiB and up to four per CU (two resident) from
-    8 MiB; explicit fields override; 64 copies always mean two tables."""
+RULE_CHECK = r"""
+import torch
+import paper_2607_02630_amd as A
+cus = torch.cuda.get_device_properties(0).multi_processor_count
+MiB = 1 << 20
+
+
+def shape(bits, size, **kw):
+    return A.launch_shape(bits, size, A.launch_cfg(**kw) if kw else None)
+
+
+# The rule works in blocks per CU; these sizes are the MI355X ones (256 CUs).
+scale = cus / 256
+s = shape(128, int(1 * MiB * scale))
+assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 1), s
+s = shape(256, int(1 * MiB * scale))
+assert (s["lds_tables"], s["wg_size"]) == (2, 256), s
+s = shape(128, int(4 * MiB * scale))
+assert (s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (2, 512, 2), s
+s = shape(128, int(8 * MiB * scale))
+assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 2), s
+assert s["grid"] == 2 * cus, s          # four per CU, clamped to the 2 chunks per CU there are
+assert s["wave_groups"] == 1, s         # two workgroups per CU: each wave its own group constants
+assert shape(128, int(4 * MiB * scale))["wave_groups"] == 0
+assert shape(128, int(8 * MiB * scale), wg_size=1024)["wave_groups"] == 0
+assert shape(128, int(8 * MiB * scale), lds_tables=4)["wave_groups"] == 0
+s = shape(128, int(32 * MiB * scale))
+assert (s["wg_size"], s["blocks_per_lane"], s["grid"]) == (512, 4, 4 * cus), s
+assert shape(128, MiB, lds_copies=64)["lds_tables"] == 2
+assert shape(128, MiB, lds_tables=4)["lds_tables"] == 4
+assert shape(128, 8 * MiB, lds_tables=4)["lds_tables"] == 4
+s = shape(128, MiB, variant=2)
+assert (s["lds_copies"], s["lds_tables"]) == (0, 0), s
+s = shape(128, MiB, variant=3, blocks_per_lane=4)
+assert (s["variant"], s["lds_copies"], s["lds_tables"], s["blocks_per_lane"]) == (3, 0, 0, 1), s
+print("rule ok")
+"""
+
+
+def test_default_shapes_pick_the_lds_layout_by_size(tmp_path):
+    """The shape rule the library falls back on without a tune cache (run in
+    a process whose cache path names no file): two T-tables (64 KiB of LDS)
+    at every size, one workgroup per CU up to 4 MiB and up to four per CU
+    (two resident) from 8 MiB; explicit fields override; 64 copies always
+    mean two tables."""
     import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, AESCTR_TUNE_CACHE=str(tmp_path / "none.json"))
+    r = subprocess.run([sys.executable, "-c", RULE_CHECK], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0 and "rule ok" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
+
+
+def test_first_chunk_modes_on_request():
+    """wave_groups on input picks the T-table kernel's first-chunk mode;
+    aes_ctr_launch_shape reports it, and refuses a mode the shape is not
+    built for."""
     A = lib()
-    here = os.path.dirname(os.path.abspath(A.lib._name))
-    if os.environ.get("AESCTR_TUNE_CACHE") or os.path.exists(os.path.join(here, "tune_cache.json")):
-        pytest.skip("a tune cache overrides the default shapes")
-    cus = torch_cuda().cuda.get_device_properties(0).multi_processor_count
     MiB = 1 << 20
-
-    def shape(bits, size, **kw):
-        return A.launch_shape(bits, size, A.launch_cfg(**kw) if kw else None)
-
-    # The rule works in blocks per CU; these sizes are the MI355X ones (256 CUs).
-    scale = cus / 256
-    s = shape(128, int(1 * MiB * scale))
-    assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 1), s
-    s = shape(256, int(1 * MiB * scale))
-    assert (s["lds_tables"], s["wg_size"]) == (2, 256), s
-    s = shape(128, int(4 * MiB * scale))
-    assert (s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (2, 512, 2), s
-    s = shape(128, int(8 * MiB * scale))
-    assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 2), s
-    assert s["grid"] == 2 * cus, s          # four per CU, clamped to the 2 chunks per CU there are
-    assert s["wave_groups"] == 1, s         # two workgroups per CU: each wave its own group constants
-    assert shape(128, int(4 * MiB * scale))["wave_groups"] == 0
-    assert shape(128, int(8 * MiB * scale), wg_size=1024)["wave_groups"] == 0
-    assert shape(128, int(8 * MiB * scale), lds_tables=4)["wave_groups"] == 0
-    s = shape(128, int(32 * MiB * scale))
-    assert (s["wg_size"], s["blocks_per_lane"], s["grid"]) == (512, 4, 4 * cus), s
-    assert shape(128, MiB, lds_copies=64)["lds_tables"] == 2
-    assert shape(128, MiB, lds_tables=4)["lds_tables"] == 4
-    assert shape(128, 8 * MiB, lds_tables=4)["lds_tables"] == 4
-    s = shape(128, MiB, variant=2)
-    assert (s["lds_copies"], s["lds_tables"]) == (0, 0), s
-    s = shape(128, MiB, variant=3, blocks_per_lane=4)
-    assert (s["variant"], s["lds_copies"], s["lds_tables"], s["blocks_per_lane"]) == (3, 0, 0, 1), s
+    base = dict(variant=1, lds_copies=32, lds_tables=2, blocks_per_lane=1, wg_size=512)
+    assert A.launch_shape(128, MiB, A.launch_cfg(wave_groups=1, **base))["wave_groups"] == 1
+    assert A.launch_shape(128, MiB, A.launch_cfg(wave_groups=2, **base))["wave_groups"] == 2
+    assert A.launch_shape(128, MiB, A.launch_cfg(wave_groups=3, **base))["wave_groups"] == 0
+    for bad in (dict(base, blocks_per_lane=4, wave_groups=2), dict(base, wg_size=1024, wave_groups=1),
+                dict(base, lds_tables=4, wave_groups=1)):
+        with pytest.raises(A.AesError) as e:
+            A.launch_shape(128, MiB, A.launch_cfg(**bad))
+        assert e.value.status == -1, bad
+        g = np.random.default_rng(3)
+        key, nonce = g.bytes(16), g.bytes(12)
+        with pytest.raises(A.AesError):
+            gpu_crypt(key, nonce, 1, W.payload(g, 4096), cfg=A.launch_cfg(**bad))

@@ -42,6 +42,7 @@ for e in cache["entries"]:
     assert shape["blocks_per_lane"] == e["bpl"] and shape["wg_size"] == e["wg"], (e, shape)
     if e["variant"] == 1:
         assert shape["lds_copies"] == e["copies"] and shape["lds_tables"] == e["tables"], (e, shape)
+        assert shape["wave_groups"] == e["first"], (e, shape)
     assert shape["grid"] <= e["grid_per_cu"] * cus, (e, shape)
     key, nonce = W.sweep_key(bits)
     x = torch.from_numpy(W.sweep_payload(size, bits)).cuda()
@@ -57,7 +58,7 @@ def test_autotune_writes_a_cache_the_library_uses(tmp_path):
     out = tmp_path / "tune_cache.json"
     env = dict(os.environ)
     env.pop("AESCTR_TUNE_CACHE", None)
-    r = subprocess.run([sys.executable, "-m", "paper_2607_02630_amd.autotune", "--sizes",
+    r = subprocess.run([sys.executable, "-m", "paper_2607_02630_amd.autotune", "--quick", "--sizes",
                         ",".join(map(str, SIZES)), "--no-batch", "--out", str(out), "--golden", GOLDEN],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
@@ -90,6 +91,6 @@ def test_batch_tuner_checks_every_candidate(tmp_path):
     batch = [e for e in cache["entries"] if e["variant"] == 10]
     assert len(batch) == 1
     e = batch[0]
-    assert e["tiles_per_cu"] in (8, 16, 32) and e["max_tile_bytes"] in (65536, 262144, 1 << 20)
+    assert e["tiles_per_cu"] == 16 and e["max_tile_bytes"] in (16384, 32768, 65536, 131072, 262144)
     assert e["bpl"] in (1, 2)
-    assert r.stdout.count('"batch"') == 18
+    assert r.stdout.count('"batch"') == 10
