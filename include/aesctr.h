@@ -284,7 +284,7 @@ typedef struct {
 
 typedef struct {
     uint64_t submitted, completed, rejected, batches;
-    uint64_t bytes_completed;
+    uint64_t bytes_completed;       /* payload bytes of the completed requests */
     uint64_t budget_high_water;     /* max bytes admitted at once */
     uint64_t queued_now, inflight_now;
     double mean_batch_reqs;

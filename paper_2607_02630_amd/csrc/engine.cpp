@@ -456,6 +456,7 @@ extern "C" int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t
             r.rec.d.out = dout;
         }
         r.bytes = d->len + 32 + sizeof(aesctr::ShaRecord);
+        r.payload = d->len;
         return e->core.submit(std::move(r), ticket, t_arrival_ns);
     }
     if ((rc = aesctr::check_desc(*d)) != AES_OK)
@@ -464,6 +465,7 @@ extern "C" int aes_submit_at(aes_engine_t *e, const aes_ctr_desc_t *d, int64_t t
     // and output, once when in place) and its staged records (descriptor and,
     // unless its key is resident, an inline key record).
     r.bytes = (d->in == d->out ? 1 : 2) * d->len + aes_engine_request_overhead();
+    r.payload = d->len;
     aesctr::make_batch_record(*d, &r.rec);
     if (e->host_buffers && d->len > 0) {
         // The kernel reads and writes the pinned host buffers directly.

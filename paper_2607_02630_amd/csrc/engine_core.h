@@ -51,6 +51,7 @@ template <class Record>
 struct EngineReq {
     uint64_t ticket = 0;
     uint64_t bytes = 0;        // admission weight: bytes the request holds in flight
+    uint64_t payload = 0;      // payload bytes, counted against the per-launch cap
     int64_t t_submit_ns = 0;
     Record rec{};
 };
@@ -197,12 +198,12 @@ public:
     // Driver thread -------------------------------------------------------
 
     // Move the longest FIFO prefix that fits the budget (and the per-launch
-    // limits) into `out`.  A head that does not fit blocks the ones behind it,
-    // so no request is overtaken forever.
+    // limits: requests, and payload bytes) into `out`.  A head that does not
+    // fit blocks the ones behind it, so no request is overtaken forever.
     bool take_batch(std::vector<Req> &out)
     {
         out.clear();
-        uint64_t batch_bytes = 0;
+        uint64_t batch_payload = 0;
         uint64_t inflight = inflight_bytes_.load(std::memory_order_relaxed);
         uint64_t deq = deq_.load(std::memory_order_relaxed);
         while (out.size() < max_reqs_) {
@@ -212,10 +213,10 @@ public:
             const uint64_t b = c.req.bytes;
             if (inflight + b > budget_)
                 break;
-            if (!out.empty() && batch_bytes + b > max_bytes_)
+            if (!out.empty() && batch_payload + c.req.payload > max_bytes_)
                 break;
             inflight += b;
-            batch_bytes += b;
+            batch_payload += c.req.payload;
             out.push_back(std::move(c.req));
             c.seq.store(deq + kQueueCap, std::memory_order_release);   // free for a producer
             ++deq;
@@ -234,14 +235,16 @@ public:
 
     void complete(const std::vector<Req> &batch, int status, int64_t now)
     {
-        uint64_t bytes = 0;
-        for (const Req &r : batch)
+        uint64_t bytes = 0, payload = 0;
+        for (const Req &r : batch) {
             bytes += r.bytes;
+            payload += r.payload;
+        }
         {
             std::lock_guard<std::mutex> lk(stats_mu_);
             if (status == AES_OK) {
                 completed_ += batch.size();
-                bytes_completed_ += bytes;
+                bytes_completed_ += payload;
                 for (const Req &r : batch)
                     if (lat_us_.size() < kMaxSamples)
                         lat_us_.push_back(static_cast<float>((now - r.t_submit_ns) * 1e-3));

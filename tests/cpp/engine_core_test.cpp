@@ -91,6 +91,7 @@ int main()
                 Core::Req r;
                 double u = std::uniform_real_distribution<double>(0, 1)(g);
                 r.bytes = sizes[u < 0.70 ? 0 : u < 0.95 ? 1 : 2];
+                r.payload = r.bytes;
                 uint64_t tk;
                 CHECK(core.submit(std::move(r), &tk) == AES_OK);
                 tickets[k].push_back(tk);
@@ -135,6 +136,31 @@ int main()
     CHECK(idle.wait(tk, 1000) == AES_ETIMEDOUT);
     idle.cancel_queued(AES_ECANCELED);
     CHECK(idle.poll(tk) == AES_ECANCELED);
+    // The per-launch cap counts payload bytes, the budget counts the weight
+    // (buffers + records): out-of-place requests of 400 payload bytes weigh
+    // 800 + 320; a 1000-byte cap takes two per launch, and the budget of
+    // 3 * 1120 admits three in flight.
+    {
+        Core capq(3 * 1120, 64, 1000);
+        for (int i = 0; i < 5; ++i) {
+            Core::Req rq;
+            rq.payload = 400;
+            rq.bytes = 2 * 400 + 320;
+            uint64_t tk3;
+            CHECK(capq.submit(std::move(rq), &tk3) == AES_OK);
+        }
+        std::vector<Core::Req> b1, b2, b3;
+        CHECK(capq.take_batch(b1) && b1.size() == 2);
+        CHECK(capq.take_batch(b2) && b2.size() == 1);     // budget: 3 in flight
+        CHECK(!capq.take_batch(b3));
+        capq.complete(b1, AES_OK, Core::now_ns());
+        CHECK(capq.take_batch(b3) && b3.size() == 2);
+        aes_stats_t cs;
+        capq.stats(&cs);
+        CHECK(cs.budget_high_water == 3 * 1120 && cs.bytes_completed == 800);
+        capq.complete(b2, AES_OK, Core::now_ns());
+        capq.complete(b3, AES_OK, Core::now_ns());
+    }
     // Back-pressure: with no driver the ring fills; the next submitter waits
     // until the driver takes requests, then goes on.
     {
