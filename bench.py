@@ -361,6 +361,39 @@ def openssl_ctr_context(size, bits, threads, seconds=3.0):
             "kind": "OpenSSL EVP AES-CTR (AES-NI), labelled context only"}
 
 
+def tune_source(A, variant, bits, size, shape=None):
+    """Where a launch shape comes from: the library reads the autotuner's
+    cache (AESCTR_TUNE_CACHE, else tune_cache.json beside libaesctr.so) and
+    takes the entry of the same variant and key size whose size_log2 is
+    floor(log2(size)); without one it keeps its built-in rule.  Reports that
+    entry, the cache's timestamp, and whether the shape in use is the entry's
+    (variant 10 is the batch kernel's tiling)."""
+    path = os.environ.get("AESCTR_TUNE_CACHE") or os.path.join(os.path.dirname(A._native.LIB_PATH),
+                                                              "tune_cache.json")
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        return {"source": "built-in rule (no tune cache)"}
+    want = max(size, 1).bit_length() - 1
+    best = None
+    for e in cache.get("entries", []):
+        if e.get("variant") == variant and (variant == 10 or (e.get("key_bits") == bits
+                                                              and e.get("size_log2") == want)):
+            best = e
+            break
+    if best is None:
+        return {"source": "built-in rule (no matching entry)", "cache": os.path.basename(path)}
+    out = {"source": "autotuner cache", "cache": os.path.basename(path), "generated": cache.get("generated"),
+           "entry": best}
+    if shape is not None and variant == 1:
+        out["shape_matches_entry"] = (shape["blocks_per_lane"] == best["bpl"] and shape["wg_size"] == best["wg"]
+                                      and shape["lds_copies"] == best["copies"]
+                                      and shape["lds_tables"] == best["tables"]
+                                      and shape["wave_groups"] == best.get("first", shape["wave_groups"]))
+    return out
+
+
 def cpu_baseline(W, size, bits, seconds):
     """The oracle, untuned, on the host cores: repeated passes over one
     benchmark buffer with all threads (median pass rate over about
@@ -495,7 +528,10 @@ def main():
                    "launches_per_step": K,
                    "timed_launch": f"each step replays a captured HIP graph of {K} launches "
                                    f"({us_per_launch:.3f} us each)",
-                   "parity_vs_oracle_digest": parity},
+                   "parity_vs_oracle_digest": parity,
+                   "shape": A.launch_shape(args.bits, args.size, cfg),
+                   "shape_source": tune_source(A, args.variant or 1, args.bits, args.size,
+                                               A.launch_shape(args.bits, args.size, cfg))},
         "roofline": {"bound": "alu", "achieved": round(gbs, 3), "peak": round(alu_peak_gbs, 1),
                      "unit": "GB/s", "frac": round(gbs / alu_peak_gbs, 4),
                      "traffic": measured_traffic(args.bits, args.size, args.variant),
@@ -557,7 +593,8 @@ def one_mib_leg(torch, A, W, sched, nonce, args):
     us = t.ms * 1e3 / (args.steps * K)
     shape = A.launch_shape(args.bits, size)
     out = {"gbps": round(size / (us * 1e-6) / 1e9, 3), "us_per_launch": round(us, 3), "steps": args.steps,
-           "launches_per_step": K, "buffers_rotated": len(ins), "parity_vs_oracle_digest": True, "shape": shape}
+           "launches_per_step": K, "buffers_rotated": len(ins), "parity_vs_oracle_digest": True, "shape": shape,
+           "shape_source": tune_source(A, 1, args.bits, size, shape)}
     log(f"1 MiB: {args.steps} steps of {K} launches, {us:.3f} us/launch, {out['gbps']:.1f} GB/s")
     del ins, outs
     torch.cuda.empty_cache()
@@ -687,7 +724,8 @@ def batch_leg(torch, A, W, reps=5):
            "per_request_graph_ms": round(gr_ms, 3), "per_request_graph_gbps": round(total / gr_ms / 1e6, 2),
            "sync_per_request_ms": round(s_ms, 3), "sync_per_request_gbps": round(total / s_ms / 1e6, 2),
            "speedup_vs_launches": round(e_ms / b_ms, 2), "speedup_vs_graph_launches": round(gr_ms / b_ms, 2),
-           "key_expansion_us_per_key": round(expand_us, 2), "parity_sampled_vs_oracle": True}
+           "key_expansion_us_per_key": round(expand_us, 2), "parity_sampled_vs_oracle": True,
+           "tiling_source": tune_source(A, 10, 0, 0)}
     log(f"batch leg: {out}")
     del g, src, dst
     torch.cuda.empty_cache()

@@ -152,7 +152,8 @@ int aes_ctr_crypt_cfg(const aes_sched_t *sched, const uint8_t nonce[12], uint32_
 
 /* The launch shape aes_ctr_crypt_cfg would use for a len-byte message with
  * this key size and cfg (NULL = defaults): the default shape, or the tune
- * cache's entry for the nearest size, overridden by cfg's non-zero fields,
+ * cache's entry for the same floor(log2(len)) where it has one, overridden
+ * by cfg's non-zero fields,
  * with the grid clamped to the work.  All fields of *out are set (variant 1,
  * 2 or 3, never AUTO; lds_copies and lds_tables 0 for the kernels without
  * T-tables).  Host only; it

@@ -101,20 +101,16 @@ bool tune_lookup(int variant, int key_bits, uint64_t len, TuneEntry *out)
 {
     std::call_once(g_once, load);
     const int want = floor_log2(len ? len : 1);
-    const TuneEntry *best = nullptr;
     for (const TuneEntry &e : g_entries) {
-        if (e.variant != variant || e.key_bits != key_bits)
+        if (e.variant != variant || e.key_bits != key_bits || e.size_log2 != want)
             continue;
         if (e.variant == 1 && ((e.copies != 32 && e.copies != 64) || (e.tables != 0 && e.tables != 2 && e.tables != 4) ||
                                (e.copies == 64 && e.tables == 4)))
             continue;
-        if (!best || abs(e.size_log2 - want) < abs(best->size_log2 - want))
-            best = &e;
+        *out = e;
+        return true;
     }
-    if (!best)
-        return false;
-    *out = *best;
-    return true;
+    return false;
 }
 
 bool tune_lookup_batch(TuneEntry *out)

@@ -10,7 +10,8 @@
 // The batch kernel's entry has "variant": 10 and carries "tiles_per_cu" and
 // "max_tile_bytes" (the tile sizing rule's constants) and "bpl".
 // A lookup takes the entry of the same variant and key size whose size_log2
-// is nearest to floor(log2(len)).
+// equals floor(log2(len)); a size the tuner did not time has no entry and
+// keeps the built-in rule.
 #pragma once
 
 #include <stdint.h>
