@@ -67,6 +67,23 @@ struct CtrArgs {
     uint32_t rk[60];
 };
 
+// The key material of CtrArgs as a kernel argument of its own, after the
+// scalars (which the dispatcher can then preload into SGPRs).
+struct CtrKeys {
+    uint32_t k1[4];
+    uint32_t rk[60];
+};
+
+inline CtrKeys ctr_keys(const CtrArgs &a)
+{
+    CtrKeys k;
+    for (int i = 0; i < 4; ++i)
+        k.k1[i] = a.k1[i];
+    for (int i = 0; i < 60; ++i)
+        k.rk[i] = a.rk[i];
+    return k;
+}
+
 // Device facts the launchers need, cached per device.
 struct DeviceInfo {
     int ordinal;

@@ -96,10 +96,27 @@ __device__ __forceinline__ uint32_t first_ctr(const CtrArgs &a, uint64_t start, 
 // kFirstFull -- the first chunk runs rounds 1-2 in full (15 more lookups
 // per block, no group constants and no second barrier).  Later chunks
 // compute theirs on the scalar unit.
+//
+// The scalars come first in the argument list, apart from the key material,
+// so the dispatcher preloads them into SGPRs (the build asks for kernel
+// argument preloading) and the first data loads need no argument fetch.
 template <int NR, int LAYOUT, int BPL, int WG, bool ALIGNED, int FIRST>
-__global__ __launch_bounds__(WG) void ctr_ttable_kernel(const CtrArgs a)
+__global__ __launch_bounds__(WG) void ctr_ttable_kernel(const uint8_t *in, uint8_t *out, uint64_t len,
+                                                        uint32_t ctr0, uint32_t x0, const CtrKeys keys)
 {
     static_assert(FIRST == kFirstWave0 || BPL <= 2, "the other first-chunk modes are built for 1-2 blocks per lane");
+    CtrArgs a;
+    a.in = in;
+    a.out = out;
+    a.len = len;
+    a.ctr0 = ctr0;
+    a.x0 = x0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        a.k1[i] = keys.k1[i];
+#pragma unroll
+    for (int i = 0; i < 4 * (NR + 1); ++i)
+        a.rk[i] = keys.rk[i];
     __shared__ uint32_t lds[layout_lds_words(LAYOUT)];
 
     const uint64_t nfull = a.len >> 4;
@@ -204,12 +221,14 @@ template <int NR, int LAYOUT, int BPL, int WG, int FIRST>
 int launch_g(const CtrArgs &a, const Shape &sh, hipStream_t st)
 {
     const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
+    const CtrKeys keys = ctr_keys(a);
     (void)hipGetLastError();   // not ours: left by earlier calls
     if (aligned)
-        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true, FIRST>), dim3(sh.grid), dim3(WG), 0, st, a);
+        hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, true, FIRST>), dim3(sh.grid), dim3(WG), 0, st,
+                           a.in, a.out, a.len, a.ctr0, a.x0, keys);
     else
         hipLaunchKernelGGL((ctr_ttable_kernel<NR, LAYOUT, BPL, WG, false, FIRST>), dim3(sh.grid), dim3(WG), 0, st,
-                           a);
+                           a.in, a.out, a.len, a.ctr0, a.x0, keys);
     return launch_status();
 }
 
