@@ -302,10 +302,9 @@ def measured_traffic(bits, size, variant):
 # computing its first chunk's group constants).
 VALU_PER_BLOCK_8MIB = {128: 347.0, 256: 467.0}
 # VALU lane operations per block of the kernels without LDS tables: the
-# bitsliced kernel (rocprofv3 SQ_INSTS_VALU at 256 MiB) and the
-# vector-permute kernel (instructions per keystream block in the built code).
+# bitsliced and the vector-permute kernels (rocprofv3 SQ_INSTS_VALU at 256 MiB).
 VALU_PER_BLOCK_BS = {128: 814, 256: 1096}
-VALU_PER_BLOCK_VP = {128: 2311, 256: 3307}
+VALU_PER_BLOCK_VP = {128: 2047, 256: 3012}
 
 
 def valu_roofline(args, gbs, cus, clk):

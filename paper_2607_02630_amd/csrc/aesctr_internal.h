@@ -112,9 +112,10 @@ int launch_ctr_bitslice(const CtrArgs &a, int nr, const Shape &sh, hipStream_t s
 
 // Arguments of the vector-permute kernel (ctr_vperm.hip): the round keys in
 // the (i, k) nibble form of its tower field, row words (byte c = column c).
-//   i0/k0   round-0 state of columns 0-2 (nonce ^ rk0), column 3 left 0
 //   x0      rk0's counter column in standard bytes (byte r = row r)
-//   rki/rkk rounds 1..Nr-1: (round key ^ {63}) in i and k nibbles
+//   rki/rkk index 0: round 1's output rows without their counter terms
+//           (the nonce columns' MixColumns terms, rk1 and the {63} fold);
+//           index t - 1, t = 2..Nr-1: (round key t ^ {63}), in i and k nibbles
 //   rkn     round Nr: (round key ^ {63}) in standard bytes
 struct VpArgs {
     const uint8_t *in;
@@ -122,7 +123,6 @@ struct VpArgs {
     uint64_t len;
     uint32_t ctr0;
     uint32_t x0;
-    uint32_t i0[4], k0[4];
     uint32_t rki[13][4], rkk[13][4];
     uint32_t rkn[4];
 };

@@ -24,11 +24,16 @@
 // k-nibble words, so ShiftRows is a rotate of each row word and MixColumns is
 // a XOR of row words:
 //   out_r = 2 S_r ^ 2 S_(r+1) ^ S_(r+1) ^ S_(r+2) ^ S_(r+3) ^ rk_r.
-// Round 0: columns 0-2 (nonce ^ rk0) arrive in (i, k) form from the host; the
-// counter column is converted in the kernel (four nibble lookups).  The
+// Round 1 is cached (counter mode): columns 0-2 of the round-0 state are the
+// constant nonce xor rk0, and after ShiftRows output column c takes exactly
+// one counter byte, the one of row 3 - c.  So one inversion chain on the
+// counter column's four bytes (converted to (i, k) form in the kernel, four
+// nibble lookups) gives every varying term of round 1, and the host folds the
+// rest of each output row, with rk1, into one constant per row.  The
 // keystream leaves as standard bytes, transposed back to column words.
 #include <string.h>
 
+#include "aes_tables.h"
 #include "aesctr_internal.h"
 
 namespace aesctr {
@@ -108,12 +113,40 @@ __device__ __forceinline__ uint32_t out_of(const Chain &c)
     return xor3(f.a, f.b, g.a) ^ g.b;
 }
 
+// MixColumns coefficient of row rp's byte in output row r: {02} on the
+// diagonal, {03} just right of it, {01} elsewhere.
+constexpr int mix_coef(int r, int rp) { return rp == r ? 2 : rp == ((r + 1) & 3) ? 3 : 1; }
+
+// Round 1, output row r: byte c holds coefficient mix_coef(r, 3 - c) times
+// S'(x_(3-c)), x_j being the counter column's byte of row j.  With S (byte j
+// = S'(x_j)), D = 2S and T = S ^ D = 3S: row1_sel picks S or T bytes (from
+// v_perm_b32(T, S, .)), 0x0c zeroes the {02} byte, and row1_dsel places D's
+// byte there (from v_perm_b32(D, D, .)).
+constexpr uint32_t row1_sel(int r)
+{
+    uint32_t s = 0;
+    for (int c = 0; c < 4; ++c) {
+        const int rp = 3 - c, k = mix_coef(r, rp);
+        s |= static_cast<uint32_t>(k == 1 ? rp : k == 3 ? 4 + rp : 12) << (8 * c);
+    }
+    return s;
+}
+constexpr uint32_t row1_dsel(int r)
+{
+    uint32_t s = 0;
+    for (int c = 0; c < 4; ++c) {
+        const int rp = 3 - c;
+        s |= static_cast<uint32_t>(rp == r ? rp : 12) << (8 * c);
+    }
+    return s;
+}
+
 // Keystream block of counter value ctr (already ctr0 + j) -> column words.
 template <int NR>
 __device__ __forceinline__ void keystream_vp(const VpArgs &a, uint32_t ctr, uint32_t (&ks)[4])
 {
-    // Round 0: the counter column xor rk0 in standard bytes (byte r = row r),
-    // converted to (i, k) nibbles and dropped into column 3 of each row.
+    // Round 0 of the counter column: ctr xor rk0 in standard bytes (byte r =
+    // row r), converted to (i, k) nibbles.
     const uint32_t X = vperm(ctr, ctr, 0x00010203u) ^ a.x0;
     const uint32_t lo = (X & 0x07070707u) | ((X << 4) & kHi);
     const uint32_t hi = ((X >> 4) & 0x07070707u) | (X & kHi);
@@ -122,15 +155,22 @@ __device__ __forceinline__ void keystream_vp(const VpArgs &a, uint32_t ctr, uint
     const Pair kl = look<kVp_cvk_lo>(lo, loc), kh = look<kVp_cvk_hi>(hi, hic);
     const uint32_t XI = xor3(il.a, il.b, ih.a) ^ ih.b;
     const uint32_t XK = xor3(kl.a, kl.b, kh.a) ^ kh.b;
+    // Round 1: one chain for the four counter bytes; the rest of each row is
+    // the host's constant (rki[0] / rkk[0]).
     uint32_t I[4], K[4];
+    {
+        const Chain c = chain(XI, XK);
+        const uint32_t SI = out_of<kVp_si_f, kVp_si_g>(c), SK = out_of<kVp_sk_f, kVp_sk_g>(c);
+        const uint32_t DI = out_of<kVp_di_f, kVp_di_g>(c), DK = out_of<kVp_dk_f, kVp_dk_g>(c);
+        const uint32_t TI = SI ^ DI, TK = SK ^ DK;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint32_t sel = 0x00020100u | static_cast<uint32_t>(4 + r) << 24;
-        I[r] = vperm(XI, a.i0[r], sel);
-        K[r] = vperm(XK, a.k0[r], sel);
+        for (int r = 0; r < 4; ++r) {
+            I[r] = xor3(vperm(TI, SI, row1_sel(r)), vperm(DI, DI, row1_dsel(r)), a.rki[0][r]);
+            K[r] = xor3(vperm(TK, SK, row1_sel(r)), vperm(DK, DK, row1_dsel(r)), a.rkk[0][r]);
+        }
     }
 #pragma unroll
-    for (int t = 1; t < NR; ++t) {
+    for (int t = 2; t < NR; ++t) {
         uint32_t SI[4], SK[4], DI[4], DK[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -228,18 +268,40 @@ void make_vperm_args(const aes_sched_t &s, const uint8_t nonce[12], uint32_t ctr
     // Byte r of column c of round key t: byte r (from the top) of schedule
     // word 4t + c (FIPS-197 words are big-endian packed).
     auto rk = [&](int t, int c, int r) { return (s.rk[4 * t + c] >> (24 - 8 * r)) & 0xffu; };
+    for (int r = 0; r < 4; ++r)
+        a->x0 |= rk(0, 3, r) << (8 * r);
+    // Round 1's constant part.  Output column c (a word, byte r = row r) is
+    // rk1's column c xor the S-box-and-MixColumns terms tr(r', b) of the
+    // three constant bytes b = state(r', c + r') (columns 0-2 of nonce xor
+    // rk0, r' != 3 - c), xor the MixColumns term of {63} in row 3 - c: the
+    // kernel adds that row's counter term from the S - {63} tables.
+    uint32_t col[4];
+    for (int c = 0; c < 4; ++c) {
+        uint32_t w = 0;
+        for (int r = 0; r < 4; ++r)
+            w |= rk(1, c, r) << (8 * r);
+        for (int rp = 0; rp < 4; ++rp) {
+            if (rp == 3 - c)
+                continue;
+            const int cc = (c + rp) & 3;
+            w ^= tr(rp, static_cast<uint8_t>(nonce[4 * cc + rp] ^ rk(0, cc, rp)));
+        }
+        const uint8_t s63 = 0x63, d63 = gf_double(s63);
+        const uint32_t t63 = static_cast<uint32_t>(d63) | static_cast<uint32_t>(s63) << 8 |
+                             static_cast<uint32_t>(s63) << 16 | static_cast<uint32_t>(d63 ^ s63) << 24;
+        col[c] = w ^ rotl32(t63, 8 * (3 - c));
+    }
     for (int r = 0; r < 4; ++r) {
         uint32_t wi = 0, wk = 0;
-        for (int c = 0; c < 3; ++c) {
-            const uint32_t v = nonce[4 * c + r] ^ rk(0, c, r);
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t v = (col[c] >> (8 * r)) & 0xffu;
             wi |= part_i(v) << (8 * c);
             wk |= part_k(v) << (8 * c);
         }
-        a->i0[r] = wi;
-        a->k0[r] = wk;
-        a->x0 |= rk(0, 3, r) << (8 * r);
+        a->rki[0][r] = wi;
+        a->rkk[0][r] = wk;
     }
-    for (int t = 1; t < nr; ++t)
+    for (int t = 2; t < nr; ++t)
         for (int r = 0; r < 4; ++r) {
             uint32_t wi = 0, wk = 0;
             for (int c = 0; c < 4; ++c) {

@@ -58,10 +58,16 @@ def rotr(x: int, n: int) -> int:
     return ((x >> n) | (x << (32 - n))) & M32 if n else x
 
 
+def mix_coef(r: int, rp: int) -> int:
+    """MixColumns coefficient of row rp's byte in output row r."""
+    return 2 if rp == r else 3 if rp == (r + 1) % 4 else 1
+
+
 def prep(key: bytes, nonce: bytes, to_parts):
-    """Round-key material as the kernel takes it: per round t >= 1 and row r
-    the parts words of (round key t) xor {63} (bytes = columns), the final
-    round's standard bytes, the initial columns 0-2 in parts and x0."""
+    """Round-key material as the kernel takes it: per round t >= 2 and row r
+    the parts words of (round key t) xor {63}; for round 1 the constant part
+    of each output row (the nonce columns' MixColumns terms, rk1, and the
+    {63} fold of the counter term); the final round's standard bytes; x0."""
     nr, w = oracle.expand(key)
     rk = [[(w[4 * t + c] >> (24 - 8 * r)) & 0xFF for c in range(4) for r in range(4)] for t in range(nr + 1)]
     # rk[t][4c + r] = byte r of column c of round key t
@@ -72,15 +78,46 @@ def prep(key: bytes, nonce: bytes, to_parts):
     rki = [[parts_word([rk[t][4 * c + r] ^ 0x63 for c in range(4)], 0) for r in range(4)] for t in range(nr + 1)]
     rkk = [[parts_word([rk[t][4 * c + r] ^ 0x63 for c in range(4)], 1) for r in range(4)] for t in range(nr + 1)]
     rkn = [sum((rk[nr][4 * c + r] ^ 0x63) << (8 * c) for c in range(4)) for r in range(4)]
-    s0 = [[nonce[4 * c + r] ^ rk[0][4 * c + r] for c in range(3)] for r in range(4)]
-    i0 = [parts_word(s0[r], 0) for r in range(4)]
-    k0 = [parts_word(s0[r], 1) for r in range(4)]
+    # Round 1 (FIPS-197 Sec. 5.1): after ShiftRows, state byte (r', c) is
+    # round-0 byte (r', c + r'), and output column c's counter byte is the
+    # one of row 3 - c.  Everything else of output byte (r, c) is constant.
+    sbox = [int(v) for v in oracle.sbox()]
+    state0 = [[nonce[4 * c + r] ^ rk[0][4 * c + r] for c in range(3)] for r in range(4)]
+    const1 = [[0] * 4 for _ in range(4)]
+    for r in range(4):
+        for c in range(4):
+            v = rk[1][4 * c + r] ^ oracle.gf_mul(mix_coef(r, 3 - c), 0x63)
+            for rp in range(4):
+                if rp != 3 - c:
+                    v ^= oracle.gf_mul(mix_coef(r, rp), sbox[state0[rp][(c + rp) % 4]])
+            const1[r][c] = v
+    rki[1] = [parts_word(const1[r], 0) for r in range(4)]
+    rkk[1] = [parts_word(const1[r], 1) for r in range(4)]
     x0 = sum(rk[0][12 + r] << (8 * r) for r in range(4))
-    return nr, rki, rkk, rkn, i0, k0, x0
+    return nr, rki, rkk, rkn, x0
+
+
+def row1_selectors(r: int):
+    """v_perm_b32 selectors of round-1 output row r: byte c takes coefficient
+    mix_coef(r, 3 - c) times byte 3 - c of S (from S or T = 3S) or of D = 2S."""
+    sel = dsel = 0
+    for c in range(4):
+        rp, k = 3 - c, mix_coef(r, 3 - c)
+        sel |= (rp if k == 1 else 4 + rp if k == 3 else 12) << (8 * c)
+        dsel |= (rp if k == 2 else 12) << (8 * c)
+    return sel, dsel
+
+
+def chain(T, I: int, K: int):
+    ak = look(T["adiv"], K)
+    j = I ^ K
+    ia = look(T["inv"], I) ^ ak
+    ja = look(T["inv"], j) ^ ak
+    return look(T["inv"], ia) ^ j, look(T["inv"], ja) ^ I
 
 
 def encrypt(tabs, key_mat, ctr: int) -> bytes:
-    nr, rki, rkk, rkn, i0, k0, x0 = key_mat
+    nr, rki, rkk, rkn, x0 = key_mat
     T = tabs
     bswap = vperm(ctr, ctr, 0x00010203)
     X = bswap ^ x0
@@ -88,19 +125,22 @@ def encrypt(tabs, key_mat, ctr: int) -> bytes:
     hi = ((X >> 4) & 0x07070707) | (X & C)
     XI = look(T["cvi_lo"], lo) ^ look(T["cvi_hi"], hi)
     XK = look(T["cvk_lo"], lo) ^ look(T["cvk_hi"], hi)
-    I = [vperm(XI, i0[r], 0x00020100 | ((4 + r) << 24)) for r in range(4)]
-    K = [vperm(XK, k0[r], 0x00020100 | ((4 + r) << 24)) for r in range(4)]
-    for t in range(1, nr + 1):
+    # Round 1 from the counter column alone.
+    io1, jo1 = chain(T, XI, XK)
+    w = {name: look(T[name + "_f"], io1) ^ look(T[name + "_g"], jo1) for name in ("si", "sk", "di", "dk")}
+    I, K = [], []
+    for r in range(4):
+        sel, dsel = row1_selectors(r)
+        I.append(vperm(w["si"] ^ w["di"], w["si"], sel) ^ vperm(w["di"], w["di"], dsel) ^ rki[1][r])
+        K.append(vperm(w["sk"] ^ w["dk"], w["sk"], sel) ^ vperm(w["dk"], w["dk"], dsel) ^ rkk[1][r])
+    for t in range(2, nr + 1):
         I = [rotr(I[r], 8 * r) for r in range(4)]
         K = [rotr(K[r], 8 * r) for r in range(4)]
         io, jo = [], []
         for r in range(4):
-            ak = look(T["adiv"], K[r])
-            j = I[r] ^ K[r]
-            ia = look(T["inv"], I[r]) ^ ak
-            ja = look(T["inv"], j) ^ ak
-            io.append(look(T["inv"], ia) ^ j)
-            jo.append(look(T["inv"], ja) ^ I[r])
+            a, b = chain(T, I[r], K[r])
+            io.append(a)
+            jo.append(b)
         if t < nr:
             out = {}
             for name in ("si", "sk", "di", "dk"):
