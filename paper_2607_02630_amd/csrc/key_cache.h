@@ -161,10 +161,16 @@ private:
 
     static size_t words(uint32_t nr) { return nr <= 14 ? 4 * (nr + 1) : kWords; }
 
+    // Hashes the cipher key alone (the first Nk = nr - 6 words of a schedule
+    // are the key, FIPS-197 Sec. 5.2): a few steps per request on the driver
+    // thread instead of one per round-key word.  Equality still compares the
+    // whole schedule (`same`), so a schedule that shares its first words with
+    // another and differs later is a different key.
     static uint64_t hash(const uint32_t *rk, uint32_t nr)
     {
         uint64_t h = 0x9e3779b97f4a7c15ull ^ nr;
-        const size_t n = words(nr);
+        const size_t nk = nr >= 10 && nr <= 14 ? nr - 6 : words(nr);
+        const size_t n = nk < words(nr) ? nk : words(nr);
         for (size_t i = 0; i < n; ++i) {
             h ^= rk[i];
             h *= 0xff51afd7ed558ccdull;

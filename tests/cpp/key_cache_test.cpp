@@ -162,6 +162,24 @@ int main()
         CHECK(c.consistent());
         CHECK(c.hits() == 1 && c.misses() == 7);
     }
+    // Two schedules with the same cipher key words (the hash) that differ in
+    // a later round key are different keys: neither may hit the other's slot.
+    {
+        std::mt19937_64 g(3);
+        Key a = make_key(g, false);
+        Key t = a;
+        t.rk[37] ^= 1u;
+        KeyCache c(2);
+        KeyCache::Ref r1 = c.acquire(a.rk, a.nr);
+        CHECK(r1.install && r1.slot >= 0);
+        c.release(r1, true);
+        KeyCache::Ref r2 = c.acquire(t.rk, t.nr);       // same hash, other schedule
+        CHECK(!r2.resident && !r2.install && r2.slot < 0 && r2.pending < 0);
+        KeyCache::Ref r3 = c.acquire(a.rk, a.nr);
+        CHECK(r3.resident && r3.slot == r1.slot);
+        c.release(r3, true);
+        CHECK(c.consistent());
+    }
     // Zero slots: every request inline, nothing counted.
     {
         std::mt19937_64 g(2);
