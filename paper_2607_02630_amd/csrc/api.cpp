@@ -118,10 +118,14 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
         //            (26.6), 256 MiB 172.6 (174.9);
         //   AES-256  1 MiB 4.11 us (4.57, 256 threads), 8 MiB 9.81 (10.19),
         //            32 MiB 30.9 (37.0), 256 MiB 242 (246).
-        // Up to 4 MiB one workgroup per CU (512 threads x 1 block up to 2
-        // MiB, 256 for AES-256 up to 1 MiB, 512 x 2 at 4 MiB); from 8 MiB
-        // 512 threads x 2 blocks (x 4 from 16 MiB) with up to four
-        // workgroups per CU in the grid, two of them resident at a time.
+        // Up to 4 MiB one workgroup per CU, each running one chunk, whose
+        // rounds 1-2 run in full (first-chunk mode 2: no group constants, no
+        // second barrier): 256 threads x 1 block up to 1 MiB, 512 x 1 at
+        // 2 MiB, 512 x 2 at 4 MiB.  The autotuner's runs put that 6-10%
+        // ahead of 512 threads with wave 0 computing the group constants up
+        // to 1 MiB (1 MiB AES-128 3.32 against 3.65 us) and 2-3% at 2-4 MiB.
+        // From 8 MiB 512 threads x 2 blocks (x 4 from 16 MiB) with up to
+        // four workgroups per CU in the grid, two of them resident at a time.
         sh.grid = di.num_cus;
         sh.copies = 32;
         sh.tables = 2;
@@ -130,12 +134,15 @@ Shape default_shape(int variant, int key_bits, uint64_t len, const DeviceInfo &d
             sh.bpl = per_cu >= 4096 ? 4 : 2;
             sh.wg = 512;
             sh.grid = 4 * di.num_cus;
-        } else if (per_cu >= 1024) {
-            sh.bpl = 2; sh.wg = 512;
-        } else if (per_cu >= 512 || key_bits == 128) {
-            sh.bpl = 1; sh.wg = 512;
         } else {
-            sh.bpl = 1; sh.wg = 256;
+            if (per_cu >= 1024) {
+                sh.bpl = 2; sh.wg = 512;
+            } else if (per_cu >= 512) {
+                sh.bpl = 1; sh.wg = 512;
+            } else {
+                sh.bpl = 1; sh.wg = 256;
+            }
+            sh.wave_groups = kFirstFull;
         }
     } else if (sh.variant == AES_VARIANT_BITSLICE) {
         sh.bpl = 1;
@@ -250,11 +257,11 @@ Shape resolve_shape(int variant, int key_bits, uint64_t len, const aes_launch_cf
     if (sh.variant == AES_VARIANT_VPERM)
         sh.bpl = 1;     // one block per lane, whatever cfg asks
     clamp_grid(&sh, len);
-    // First-chunk mode of the T-table kernel.  Per-wave first-chunk group
-    // constants pay off when two workgroups with the 64 KiB image share each
-    // CU (8 MiB AES-128: 7.64-7.69 against 7.74-7.78 us); with one workgroup
-    // per CU they cost more than wave 0 computing them for all (4 MiB: 5.39
-    // against 5.30 us).
+    // First-chunk mode of the T-table kernel: cfg's, else the tuned entry's
+    // or the rule's (mode 2 up to 4 MiB) where the shape is built for it.
+    // Per-wave first-chunk group constants pay off when two workgroups with
+    // the 64 KiB image share each CU (8 MiB AES-128: 7.64-7.69 against
+    // 7.74-7.78 us); other shapes fall back to wave 0 computing them.
     const int tuned = sh.wave_groups;
     sh.wave_groups = kFirstWave0;
     if (sh.variant == AES_VARIANT_TTABLE) {

@@ -49,12 +49,15 @@ __device__ __forceinline__ uint32_t sel4(uint32_t q, uint32_t v0, uint32_t v1, u
     return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
 }
 
-// Value of v in lane (q + R) mod 4 of this lane's quad.
+// Value of v in lane (q + R) mod 4 of this lane's quad.  Every row and bank
+// is enabled and a quad permutation reads only lanes of the same quad, so
+// every lane is written: the DPP move needs no "old" value (one with
+// update_dpp costs a v_mov of the old value per exchange).
 template <int R>
 __device__ __forceinline__ uint32_t from_quad(uint32_t v)
 {
     constexpr int ctrl = ((0 + R) & 3) | (((1 + R) & 3) << 2) | (((2 + R) & 3) << 4) | (((3 + R) & 3) << 6);
-    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), ctrl, 0xF, 0xF, false));
+    return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(v), ctrl, 0xF, 0xF, false));
 }
 
 // Slices of the 32-bit counters c_i = C + 16*i (i = 0..31), C = this quad's

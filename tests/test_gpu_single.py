@@ -235,16 +235,20 @@ def shape(bits, size, **kw):
 # The rule works in blocks per CU; these sizes are the MI355X ones (256 CUs).
 scale = cus / 256
 s = shape(128, int(1 * MiB * scale))
-assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 1), s
+assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 256, 1), s
+assert s["wave_groups"] == 2, s         # one chunk per workgroup: rounds 1-2 in full
 s = shape(256, int(1 * MiB * scale))
-assert (s["lds_tables"], s["wg_size"]) == (2, 256), s
+assert (s["lds_tables"], s["wg_size"], s["wave_groups"]) == (2, 256, 2), s
+s = shape(128, int(2 * MiB * scale))
+assert (s["wg_size"], s["blocks_per_lane"], s["wave_groups"]) == (512, 1, 2), s
 s = shape(128, int(4 * MiB * scale))
 assert (s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (2, 512, 2), s
 s = shape(128, int(8 * MiB * scale))
 assert (s["lds_copies"], s["lds_tables"], s["wg_size"], s["blocks_per_lane"]) == (32, 2, 512, 2), s
 assert s["grid"] == 2 * cus, s          # four per CU, clamped to the 2 chunks per CU there are
 assert s["wave_groups"] == 1, s         # two workgroups per CU: each wave its own group constants
-assert shape(128, int(4 * MiB * scale))["wave_groups"] == 0
+assert shape(128, int(4 * MiB * scale))["wave_groups"] == 2
+assert shape(128, int(1 * MiB * scale), wg_size=1024)["wave_groups"] == 0   # mode 2 is built up to 512
 assert shape(128, int(8 * MiB * scale), wg_size=1024)["wave_groups"] == 0
 assert shape(128, int(8 * MiB * scale), lds_tables=4)["wave_groups"] == 0
 s = shape(128, int(32 * MiB * scale))
@@ -263,9 +267,9 @@ print("rule ok")
 def test_default_shapes_pick_the_lds_layout_by_size(tmp_path):
     """The shape rule the library falls back on without a tune cache (run in
     a process whose cache path names no file): two T-tables (64 KiB of LDS)
-    at every size, one workgroup per CU up to 4 MiB and up to four per CU
-    (two resident) from 8 MiB; explicit fields override; 64 copies always
-    mean two tables."""
+    at every size, one workgroup per CU with rounds 1-2 of its one chunk in
+    full up to 4 MiB, and up to four per CU (two resident) from 8 MiB;
+    explicit fields override; 64 copies always mean two tables."""
     import os
     import subprocess
     import sys
