@@ -15,8 +15,10 @@
 //   MixColumns  inside the lane: with t_r = a_r ^ a_(r+1) and
 //               T = a_0^a_1^a_2^a_3 each output byte is xtime(t_r) ^ T ^ a_r;
 //   AddRoundKey a round-key bit is the same for all 32 blocks of the lane:
-//               a 0 / ~0 mask (bit field extract of the lane's key column)
-//               folded into the MixColumns 3-input XORs.
+//               a 0 / ~0 mask folded into the MixColumns 3-input XORs.  The
+//               masks of every round and column are built once per
+//               workgroup into LDS and read back 16 bytes at a time (the
+//               kernel is bound by VALU issue; LDS is otherwise idle).
 // Counter blocks are built directly in sliced form (no transpose on the way
 // in).  Rounds 0 and 1 use the per-request constant k1 shared with the
 // T-table kernel: round 1 needs one S-box per lane, on the counter byte that
@@ -105,9 +107,51 @@ __device__ __forceinline__ void shift_rows(uint32_t (&st)[4][8])
     }
 }
 
-// MixColumns + AddRoundKey on this lane's column; k = the lane's round-key
-// column word (byte r = row r).
-__device__ __forceinline__ void mix_column(uint32_t (&a)[4][8], uint32_t k)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Round-key masks (0 or ~0, one per key bit) in LDS.  Entry e, column q:
+// e = 0: the counter column's round-0 key byte that lands in column q (row
+// 3 - q), bits 0-7; e = 1: k1[q]; e = 2..NR: round key word 4e + q; word 8r
+// + b is bit b of row r.  Rows of 36 words (144 bytes), so the 16-byte reads
+// of the four columns in one instruction start on different banks.
+constexpr int kMaskRow = 36;
+
+template <int NR>
+struct MaskTable {
+    uint32_t m[NR + 1][4][kMaskRow];
+};
+
+// Fills the table: the (column, bit) pairs are spread over the workgroup,
+// the entries unrolled so every key word index is uniform.
+template <int NR>
+__device__ __forceinline__ void fill_masks(const CtrArgs &a, MaskTable<NR> &t)
+{
+    for (uint32_t p = threadIdx.x; p < 128; p += blockDim.x) {
+        const uint32_t q = p >> 5, j = p & 31;
+        t.m[0][q][j] = j < 8 ? bitmask(a.x0, 8 * (3 - q) + j) : 0u;
+        t.m[1][q][j] = bitmask(sel4(q, a.k1[0], a.k1[1], a.k1[2], a.k1[3]), j);
+#pragma unroll
+        for (int e = 2; e <= NR; ++e)
+            t.m[e][q][j] = bitmask(sel4(q, a.rk[4 * e], a.rk[4 * e + 1], a.rk[4 * e + 2], a.rk[4 * e + 3]), j);
+    }
+}
+
+// The 32 masks of one entry for this lane's column, in registers.
+__device__ __forceinline__ void read_masks(const uint32_t *row, uint32_t (&km)[32])
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const u32x4 v = reinterpret_cast<const u32x4 *>(row)[i];
+        km[4 * i] = v[0];
+        km[4 * i + 1] = v[1];
+        km[4 * i + 2] = v[2];
+        km[4 * i + 3] = v[3];
+    }
+}
+
+// MixColumns + AddRoundKey on this lane's column; km = the masks of the
+// lane's round-key column (word 8r + b: bit b of row r).
+__device__ __forceinline__ void mix_column(uint32_t (&a)[4][8], const uint32_t (&km)[32])
 {
     uint32_t t[4][8], tot[8];
 #pragma unroll
@@ -122,14 +166,14 @@ __device__ __forceinline__ void mix_column(uint32_t (&a)[4][8], uint32_t k)
     for (int r = 0; r < 4; ++r) {
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const uint32_t km = bitmask(k, 8 * r + b);
+            const uint32_t k = km[8 * r + b];
             uint32_t v;
             if (b == 0)
-                v = xor3(xor3(t[r][7], tot[0], a[r][0]), km, 0);
+                v = xor3(xor3(t[r][7], tot[0], a[r][0]), k, 0);
             else if (b == 1 || b == 3 || b == 4)
-                v = xor3(xor3(t[r][b - 1], t[r][7], tot[b]), a[r][b], km);
+                v = xor3(xor3(t[r][b - 1], t[r][7], tot[b]), a[r][b], k);
             else
-                v = xor3(xor3(t[r][b - 1], tot[b], a[r][b]), km, 0);
+                v = xor3(xor3(t[r][b - 1], tot[b], a[r][b]), k, 0);
             a[r][b] = v;
         }
     }
@@ -172,7 +216,8 @@ __device__ __forceinline__ void transpose32(uint32_t (&w)[32])
 // Keystream of this lane's column for the quad's 32 blocks, as slices.
 // q = column, C = counter of block i = 0.
 template <int NR>
-__device__ __forceinline__ void keystream_column(const CtrArgs &a, uint32_t q, uint32_t C, uint32_t (&st)[4][8])
+__device__ __forceinline__ void keystream_column(const MaskTable<NR> &mt, uint32_t q, uint32_t C,
+                                                 uint32_t (&st)[4][8])
 {
     // Rounds 0 + 1.  The counter column x = bswap(ctr) ^ x0 has byte r equal
     // to counter byte 12 + r (big-endian) XOR byte r of x0; its byte r lands
@@ -182,13 +227,15 @@ __device__ __forceinline__ void keystream_column(const CtrArgs &a, uint32_t q, u
         uint32_t cs[32];
         counter_slices(C, cs);
         const uint32_t r = 3 - q;
+        uint32_t km[32];
+        read_masks(mt.m[0][q], km);
         uint32_t y[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b)
-            y[b] = sel4(q, cs[b], cs[8 + b], cs[16 + b], cs[24 + b]) ^ bitmask(a.x0, 8 * r + b);
+            y[b] = sel4(q, cs[b], cs[8 + b], cs[16 + b], cs[24 + b]) ^ km[b];
         sbox_bs(y);
         // Row i gets coef[(i - r) mod 4] * S(x_r), coef = {02},{01},{01},{03}.
-        const uint32_t k1c = sel4(q, a.k1[0], a.k1[1], a.k1[2], a.k1[3]);
+        read_masks(mt.m[1][q], km);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t ci = (static_cast<uint32_t>(i) - r) & 3;
@@ -196,7 +243,7 @@ __device__ __forceinline__ void keystream_column(const CtrArgs &a, uint32_t q, u
             for (int b = 0; b < 8; ++b) {
                 const uint32_t x2 = xt_bit(y, b);
                 const uint32_t v = ci == 0 ? x2 : ci == 3 ? (x2 ^ y[b]) : y[b];
-                st[i][b] = v ^ bitmask(k1c, 8 * i + b);
+                st[i][b] = v ^ km[8 * i + b];
             }
         }
     }
@@ -206,17 +253,20 @@ __device__ __forceinline__ void keystream_column(const CtrArgs &a, uint32_t q, u
         for (int r = 0; r < 4; ++r)
             sbox_bs(st[r]);
         shift_rows(st);
-        mix_column(st, sel4(q, a.rk[4 * rnd], a.rk[4 * rnd + 1], a.rk[4 * rnd + 2], a.rk[4 * rnd + 3]));
+        uint32_t km[32];
+        read_masks(mt.m[rnd][q], km);
+        mix_column(st, km);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         sbox_bs(st[r]);
     shift_rows(st);
-    const uint32_t kl = sel4(q, a.rk[4 * NR], a.rk[4 * NR + 1], a.rk[4 * NR + 2], a.rk[4 * NR + 3]);
+    uint32_t km[32];
+    read_masks(mt.m[NR][q], km);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) st[r][b] ^= bitmask(kl, 8 * r + b);
+        for (int b = 0; b < 8; ++b) st[r][b] ^= km[8 * r + b];
 }
 
 template <bool ALIGNED>
@@ -252,8 +302,15 @@ __global__ __launch_bounds__(256) void ctr_bitslice_kernel(const CtrArgs a)
     const uint64_t waves_per_wg = blockDim.x >> 6;
     const uint64_t gw = blockIdx.x * waves_per_wg + (threadIdx.x >> 6);
     const uint64_t step = static_cast<uint64_t>(gridDim.x) * waves_per_wg * 512;
+    __shared__ MaskTable<NR> mt;
+    fill_masks<NR>(a, mt);
+    __syncthreads();
 
     for (uint64_t base = gw * 512; base < nblocks; base += step) {
+        // The mask table never changes, but its reads must stay in the round
+        // that uses them: hoisted out of the loop they would hold all 352
+        // masks in registers.  A compiler-only barrier (no instruction).
+        asm volatile("" ::: "memory");
         // Data words first (block base + 16 i + g, word q); their latency
         // hides behind the rounds.
         uint32_t d[32];
@@ -264,7 +321,7 @@ __global__ __launch_bounds__(256) void ctr_bitslice_kernel(const CtrArgs a)
                 d[i] = load_word<ALIGNED>(a.in + 16 * (base + 16 * i + g) + 4 * q);
         }
         uint32_t st[4][8];
-        keystream_column<NR>(a, q, a.ctr0 + static_cast<uint32_t>(base + g), st);
+        keystream_column<NR>(mt, q, a.ctr0 + static_cast<uint32_t>(base + g), st);
         uint32_t w[32];
 #pragma unroll
         for (int k = 0; k < 32; ++k)
