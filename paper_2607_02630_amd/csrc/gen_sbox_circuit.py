@@ -18,8 +18,11 @@ derived here from the field arithmetic alone (no table is typed in):
    inverse is squaring.  Products use Karatsuba, 3 sub-products each, so the
    whole inversion has 36 AND gates; everything else is GF(2)-linear.
 3. Every linear signal is a XOR of "basis" signals (the 8 input bits and the
-   AND outputs).  The XORs needed are shared greedily (Paar's algorithm,
-   "A new algorithm for constructing small XOR circuits", 1997).
+   AND outputs).  The XORs needed are shared greedily, in the manner of
+   Paar's algorithm ("A new algorithm for constructing small XOR circuits",
+   1997) but over pairs and triples: the target's nodes take three inputs,
+   so a triple of signals that occurs in c forms saves 2c XOR terms with one
+   3-input node, and the greedy weighs it against the pairs by w3 * c.
 4. The 2-input netlist is covered with 3-input functions: a gate whose only
    reader can absorb it (at most 3 distinct leaves) is merged into that
    reader.  Each 3-input node becomes one v_bitop3_b32 with its truth table.
@@ -280,31 +283,43 @@ class Node:
         self.op, self.ins, self.tt = op, list(ins), tt
 
 
-def paar(forms: list[set], next_var: int, new_xor, rng=None):
-    """Greedy pair sharing; mutates forms until each is one variable.  Ties
-    between equally frequent pairs are broken by `rng` (or by index)."""
+def paar(forms: list[set], next_var: int, new_xor, rng=None, w3: float = 1.5):
+    """Greedy sharing of pairs and triples of signals; mutates forms until
+    each is one variable.  A pair occurring in c forms scores c, a triple
+    occurring in c >= 2 forms scores w3 * c (it becomes two 2-input XORs whose
+    inner one has no other reader, which the 3-input covering merges).  Ties
+    are broken by `rng` (or by index)."""
     while True:
-        cnt = Counter()
+        c2, c3 = Counter(), Counter()
         for f in forms:
             if len(f) >= 2:
-                for p in itertools.combinations(sorted(f), 2):
-                    cnt[p] += 1
-        if not cnt:
+                s = sorted(f)
+                for p in itertools.combinations(s, 2):
+                    c2[p] += 1
+                if len(s) >= 3:
+                    for t in itertools.combinations(s, 3):
+                        c3[t] += 1
+        if not c2:
             return next_var
-        top = max(cnt.values())
-        ties = sorted(p for p, c in cnt.items() if c == top)
-        a, b = rng.choice(ties) if rng is not None else ties[0]
+        scored = [(float(c), p) for p, c in c2.items()] + [(w3 * c, t) for t, c in c3.items() if c >= 2]
+        top = max(sc for sc, _ in scored)
+        ties = sorted(x for sc, x in scored if sc == top)
+        pick = rng.choice(ties) if rng is not None else ties[0]
         v = next_var
         next_var += 1
-        new_xor(v, a, b)
+        new_xor(v, pick[0], pick[1])
+        if len(pick) == 3:
+            inner, v = v, next_var
+            next_var += 1
+            new_xor(v, inner, pick[2])
         for f in forms:
-            if a in f and b in f:
-                f.discard(a)
-                f.discard(b)
+            if all(x in f for x in pick):
+                for x in pick:
+                    f.discard(x)
                 f.add(v)
 
 
-def build_netlist(S: Sym, outs: list[frozenset], rng=None):
+def build_netlist(S: Sym, outs: list[frozenset], rng=None, w3: float = 1.5):
     """2-input netlist in topological order.  Returns (nodes, out_vars)."""
     nodes: dict[int, Node] = {}
     order: list[int] = []
@@ -321,7 +336,7 @@ def build_netlist(S: Sym, outs: list[frozenset], rng=None):
     def new_xor(v, a, b):
         nodes[v] = Node("xor", (a, b))
 
-    next_var = paar(forms, S.nvars, new_xor, rng)
+    next_var = paar(forms, S.nvars, new_xor, rng, w3)
     for k, (a, b) in enumerate(S.ands):
         fa, fb = forms[2 * k], forms[2 * k + 1]
         assert len(fa) == 1 and len(fb) == 1
@@ -458,7 +473,7 @@ def bitsliced_inputs():
     return [sum(((x >> b) & 1) << x for x in range(256)) for b in range(8)]
 
 
-def synthesize(nu, lam, beta, rng=None):
+def synthesize(nu, lam, beta, rng=None, w3: float = 1.5):
     # to_tower: columns = tower value of beta^j (image of AES basis x^j)
     cols = []
     p = 1
@@ -475,14 +490,14 @@ def synthesize(nu, lam, beta, rng=None):
             aff[i] |= 1 << ((i + k) % 8)
     out_mat = mat_mul(aff, from_tower)
     S, outs = build_inverse(nu, lam, to_tower, out_mat)
-    nodes, order, out_vars = build_netlist(S, outs, rng)
+    nodes, order, out_vars = build_netlist(S, outs, rng, w3)
     lut = cover_lut3(nodes, order, out_vars)
     return lut, order, out_vars
 
 
-def search(seeds: int = 0):
-    """Try every tower (nu, lam, beta); for each, index tie-breaking plus
-    `seeds` seeded random tie-breakings of the XOR sharing."""
+def search(seeds: int = 0, weights=(1.5, 1.75)):
+    """Try every tower (nu, lam, beta) and triple weight w3; for each, index
+    tie-breaking plus `seeds` seeded random tie-breakings of the XOR sharing."""
     import random
     table = aes_sbox_table()
     best = None
@@ -492,9 +507,9 @@ def search(seeds: int = 0):
         for lam in range(1, 16):
             if not irreducible_quadratic(lam, lambda a, b: g16_mul(a, b, nu), 16):
                 continue
-            for beta, seed in itertools.product(tower_roots_of_aes_poly(nu, lam), range(-1, seeds)):
+            for beta, w3, seed in itertools.product(tower_roots_of_aes_poly(nu, lam), weights, range(-1, seeds)):
                 rng = random.Random(seed) if seed >= 0 else None
-                lut, order, out_vars = synthesize(nu, lam, beta, rng)
+                lut, order, out_vars = synthesize(nu, lam, beta, rng, w3)
                 # Outputs must be distinct LUT nodes (no plain input passthrough).
                 if len(set(out_vars)) != 8 or any(v < 8 for v in out_vars):
                     continue
@@ -504,12 +519,12 @@ def search(seeds: int = 0):
                     raise AssertionError(f"circuit wrong for nu={nu} lam={lam} beta={beta}")
                 cost = len(lut)
                 if best is None or cost < best[0]:
-                    best = (cost, nu, lam, beta, lut, order, out_vars, seed)
+                    best = (cost, nu, lam, beta, lut, order, out_vars, seed, w3)
     return best
 
 
 def emit(best, path):
-    cost, nu, lam, beta, lut, order, out_vars, seed = best
+    cost, nu, lam, beta, lut, order, out_vars, seed, w3 = best
     names = {i: f"x[{i}]" for i in range(8)}
     lines = []
     tmp = 0
@@ -549,7 +564,7 @@ def emit(best, path):
         "// Bitsliced AES S-box (FIPS-197 Sec. 5.1.1) as a straight-line program of",
         f"// {cost} three-input boolean functions (v_bitop3_b32), derived from the",
         f"// tower field GF(((2^2)^2)^2) with nu={nu}, lambda={lam}, beta={beta}",
-        f"// (XOR-sharing tie-break seed {seed}).",
+        f"// (XOR sharing with triple weight {w3}, tie-break seed {seed}).",
         "// x[b] holds bit b (LSB = 0) of 32 bytes; on return x[b] holds bit b of",
         "// their S-box values.  bitop3(a, b, c, T) must compute the function whose",
         "// value for inputs (a, b, c) is bit (a<<2 | b<<1 | c) of T.",
