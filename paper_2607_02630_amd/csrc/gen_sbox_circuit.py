@@ -11,12 +11,19 @@ derived here from the field arithmetic alone (no table is typed in):
      GF(256) = GF(16)[y]/(y^2 + y + lam)    lam in GF(16), polynomial irreducible
    and map the AES field into it by the GF(2)-linear isomorphism sending x
    to a root beta of the AES polynomial (Canright, "A very compact Rijndael
-   S-box", 2005, takes the same route).
-2. Invert in the tower with the norm formula for a quadratic extension:
-     (a y + b)^-1 = a D^-1 y + (a + b) D^-1,   D = lam a^2 + a b + b^2
+   S-box", 2005, takes the same route).  Each of the two upper levels holds
+   its elements in the polynomial basis {X, 1} or in the normal basis
+   {X^q, X} of its extension, as Canright compares; the change of basis is
+   linear and folds into the input and output maps.
+2. Invert in the tower with the norm formula for a quadratic extension,
+   polynomial basis:  (a y + b)^-1 = a D^-1 y + (a + b) D^-1,
+                      D = lam a^2 + a b + b^2;
+   normal basis:      (h y^16 + l y)^-1 = l D^-1 y^16 + h D^-1 y,
+                      D = lam (h + l)^2 + h l,
    applied twice (GF(256) over GF(16), GF(16) over GF(4)); in GF(4) the
-   inverse is squaring.  Products use Karatsuba, 3 sub-products each, so the
-   whole inversion has 36 AND gates; everything else is GF(2)-linear.
+   inverse is squaring.  Products use 3 sub-products each (Karatsuba, or its
+   normal-basis analogue), so the whole inversion has 36 AND gates;
+   everything else is GF(2)-linear.
 3. Every linear signal is a XOR of "basis" signals (the 8 input bits and the
    AND outputs).  The XORs needed are shared greedily, in the manner of
    Paar's algorithm ("A new algorithm for constructing small XOR circuits",
@@ -28,7 +35,8 @@ derived here from the field arithmetic alone (no table is typed in):
    reader.  Each 3-input node becomes one v_bitop3_b32 with its truth table.
    The affine constant {63} is folded into the output nodes' truth tables.
 
-The search over (nu, lam, beta) keeps the smallest circuit.  The result is
+The search over the bases, (nu, lam, beta), the triple weight and seeded
+tie-breakings keeps the smallest circuit.  The result is
 checked on all 256 inputs against the S-box computed from its definition,
 and written as straight-line C++ to sbox_circuit.inc.
 
@@ -154,13 +162,53 @@ def mat_mul(x: list[int], y: list[int], n: int = 8) -> list[int]:
 # --------------------------------------------------------------------------
 
 
+# Each level's extension X^2 + X + c (c = nu over GF(4), lam over GF(16),
+# 1 for GF(4) over GF(2)) has trace 1, so its conjugate is X^q = X + 1.  An
+# element is held in the polynomial basis {X, 1} (coordinates (a1, a0) of
+# a1 X + a0) or in the normal basis {X^q, X} (coordinates (h, l) of
+# h X^q + l X); since 1 = X + X^q, a1 X + a0 = a0 X^q + (a0 + a1) X.
+
+
+def pb_to_rep(hi: int, lo: int, normal: bool):
+    return (lo, lo ^ hi) if normal else (hi, lo)
+
+
+def rep_to_pb(h: int, l: int, normal: bool):
+    return (h ^ l, h) if normal else (h, l)
+
+
+class Rep:
+    """Coordinates of the tower in the chosen bases: normal or polynomial at
+    the GF(16)/GF(4) and GF(256)/GF(16) levels (GF(4)/GF(2) polynomial).
+    Value-level maps between the polynomial tower integers used by g4_mul /
+    g16_mul / g256_mul and these coordinates."""
+
+    def __init__(self, nu: int, lam: int, nb16: bool, nb256: bool):
+        self.nu, self.lam, self.nb16, self.nb256 = nu, lam, nb16, nb256
+
+    def r16(self, y: int) -> int:
+        h, l = pb_to_rep(y >> 2, y & 3, self.nb16)
+        return (h << 2) | l
+
+    def u16(self, y: int) -> int:
+        a1, a0 = rep_to_pb(y >> 2, y & 3, self.nb16)
+        return (a1 << 2) | a0
+
+    def r256(self, x: int) -> int:
+        h, l = pb_to_rep(self.r16(x >> 4), self.r16(x & 15), self.nb256)
+        return (h << 4) | l
+
+
 class Sym:
     """Signals are frozensets of basis variables (their XOR).  Basis
-    variables 0..7 are the input bits; each AND adds a variable."""
+    variables 0..7 are the input bits; each AND adds a variable.  GF(4)
+    elements are (hi, lo) signal pairs, GF(16) elements (H, L) pairs of GF(4)
+    elements, in the coordinates of `rep`."""
 
-    def __init__(self):
+    def __init__(self, rep: Rep):
         self.nvars = 8
         self.ands: list[tuple[frozenset, frozenset]] = []   # var 8+k = ands[k][0] & ands[k][1]
+        self.rep = rep
 
     @staticmethod
     def xor(a: frozenset, b: frozenset) -> frozenset:
@@ -174,7 +222,7 @@ class Sym:
         self.nvars += 1
         return frozenset([v])
 
-    # GF(4) element: (hi, lo) forms
+    # GF(4), polynomial basis {v, 1}, v^2 = v + 1: Karatsuba, 3 ANDs.
     def g4_mul(self, a, b):
         m1 = self.and_(a[0], b[0])
         m0 = self.and_(a[1], b[1])
@@ -199,16 +247,24 @@ class Sym:
                 lo = lo ^ form
         return (hi, lo)
 
-    # GF(16) element: (A1, A0) GF(4) elements
-    def g16_mul(self, a, b, nu):
+    # GF(16) over GF(4) with w^2 = w + nu.  Polynomial basis: Karatsuba
+    # (A1 B1, A0 B0, (A1+A0)(B1+B0)).  Normal basis {w^4, w} (w w^4 = nu):
+    # with M = (H_a + L_a)(H_b + L_b), the product is
+    # (H_a H_b + nu M) w^4 + (L_a L_b + nu M) w.  Three GF(4) products either way.
+    def g16_mul(self, a, b):
+        nu = self.rep.nu
+        if self.rep.nb16:
+            nM = self.g4_mulconst(nu, self.g4_mul(add4(a[0], a[1]), add4(b[0], b[1])))
+            return (add4(self.g4_mul(a[0], b[0]), nM), add4(self.g4_mul(a[1], b[1]), nM))
         M1 = self.g4_mul(a[0], b[0])
         M0 = self.g4_mul(a[1], b[1])
         M2 = self.g4_mul(add4(a[0], a[1]), add4(b[0], b[1]))
         return (add4(M2, M0), add4(self.g4_mulconst(nu, M1), M0))
 
     def g16_linear(self, a, fn):
-        """Apply a GF(2)-linear map on GF(16) given as a function on values."""
-        bits = [a[1][1], a[1][0], a[0][1], a[0][0]]   # value bits 0..3: lo.lo, lo.hi, hi.lo, hi.hi
+        """Apply a GF(2)-linear map on GF(16), given as a function on
+        coordinate values ((H << 2) | L), to a symbolic element."""
+        bits = [a[1][1], a[1][0], a[0][1], a[0][0]]   # value bits 0..3: L.lo, L.hi, H.lo, H.hi
         out = [frozenset()] * 4
         for i in range(4):
             img = fn(1 << i)
@@ -217,11 +273,20 @@ class Sym:
                     out[j] = out[j] ^ bits[i]
         return ((out[3], out[2]), (out[1], out[0]))
 
-    def g16_inv(self, d, nu):
-        D1, D0 = d
-        t = add4(add4(self.g4_mulconst(nu, self.g4_sq(D1)), self.g4_mul(D1, D0)), self.g4_sq(D0))
+    # Inverse by the norm: polynomial basis, (a1 w + a0)^-1 = a1 t^-1 w +
+    # (a1 + a0) t^-1 with t = nu a1^2 + a1 a0 + a0^2; normal basis,
+    # (h w^4 + l w)^-1 = l t^-1 w^4 + h t^-1 w with t = nu (h + l)^2 + h l.  In
+    # GF(4), t^-1 = t^2.
+    def g16_inv(self, d):
+        nu = self.rep.nu
+        h, l = d
+        if self.rep.nb16:
+            t = add4(self.g4_mulconst(nu, self.g4_sq(add4(h, l))), self.g4_mul(h, l))
+            ti = self.g4_sq(t)
+            return (self.g4_mul(l, ti), self.g4_mul(h, ti))
+        t = add4(add4(self.g4_mulconst(nu, self.g4_sq(h)), self.g4_mul(h, l)), self.g4_sq(l))
         ti = self.g4_sq(t)
-        return (self.g4_mul(D1, ti), self.g4_mul(add4(D1, D0), ti))
+        return (self.g4_mul(h, ti), self.g4_mul(add4(h, l), ti))
 
 
 def add4(a, b):
@@ -240,9 +305,14 @@ def g16_to_bits(e):
     return [e[1][1], e[1][0], e[0][1], e[0][0]]
 
 
-def build_inverse(nu: int, lam: int, to_tower: list[int], from_tower_affine: list[int]):
-    """Symbolic S-box: returns (Sym, list of 8 output forms)."""
-    S = Sym()
+def build_inverse(rep: Rep, to_tower: list[int], from_tower_affine: list[int]):
+    """Symbolic S-box: returns (Sym, list of 8 output forms).  GF(256) over
+    GF(16) with y^2 = y + lam; the inverse by the norm, as for GF(16):
+    polynomial basis (a y + b)^-1 = a D^-1 y + (a + b) D^-1 with
+    D = lam a^2 + a b + b^2; normal basis (h y^16 + l y)^-1 = l D^-1 y^16 +
+    h D^-1 y with D = lam (h + l)^2 + h l."""
+    S = Sym(rep)
+    nu, lam = rep.nu, rep.lam
     x = [frozenset([i]) for i in range(8)]
     # tower bits t_i = XOR_j to_tower[i]_j x_j
     t = []
@@ -252,15 +322,19 @@ def build_inverse(nu: int, lam: int, to_tower: list[int], from_tower_affine: lis
             if (to_tower[i] >> j) & 1:
                 f = f ^ x[j]
         t.append(f)
-    A = value_bits_to_g16(t[4:8])     # coefficient of y
+    A = value_bits_to_g16(t[4:8])     # coordinate of y^16 (normal) or y (polynomial)
     B = value_bits_to_g16(t[0:4])
-    sq_lam = S.g16_linear(A, lambda v: g16_mul(lam, g16_mul(v, v, nu), nu))
-    sq_b = S.g16_linear(B, lambda v: g16_mul(v, v, nu))
-    D = add16(add16(sq_lam, S.g16_mul(A, B, nu)), sq_b)
-    Di = S.g16_inv(D, nu)
-    C = S.g16_mul(A, Di, nu)
-    E = S.g16_mul(add16(A, B), Di, nu)
-    inv_bits = g16_to_bits(E) + g16_to_bits(C)      # tower value bits 0..7
+    sq = lambda v: rep.r16(g16_mul(rep.u16(v), rep.u16(v), nu))
+    lam_sq = lambda v: rep.r16(g16_mul(lam, g16_mul(rep.u16(v), rep.u16(v), nu), nu))
+    if rep.nb256:
+        D = add16(S.g16_linear(add16(A, B), lam_sq), S.g16_mul(A, B))
+        Di = S.g16_inv(D)
+        hi, lo = S.g16_mul(B, Di), S.g16_mul(A, Di)
+    else:
+        D = add16(add16(S.g16_linear(A, lam_sq), S.g16_mul(A, B)), S.g16_linear(B, sq))
+        Di = S.g16_inv(D)
+        hi, lo = S.g16_mul(A, Di), S.g16_mul(add16(A, B), Di)
+    inv_bits = g16_to_bits(lo) + g16_to_bits(hi)      # coordinate bits 0..7
     outs = []
     for i in range(8):
         f = frozenset()
@@ -473,15 +547,15 @@ def bitsliced_inputs():
     return [sum(((x >> b) & 1) << x for x in range(256)) for b in range(8)]
 
 
-def synthesize(nu, lam, beta, rng=None, w3: float = 1.5):
-    # to_tower: columns = tower value of beta^j (image of AES basis x^j)
+def synthesize(nu, lam, beta, rng=None, w3: float = 1.5, nb16: bool = False, nb256: bool = False):
+    rep = Rep(nu, lam, nb16, nb256)
+    # to_tower: columns = coordinates of beta^j (the image of AES basis x^j)
     cols = []
     p = 1
     for _ in range(8):
-        cols.append(p)
+        cols.append(rep.r256(p))
         p = g256_mul(p, beta, nu, lam)
-    to_std_cols = cols                       # maps AES-basis coords -> tower value bits
-    to_tower = mat_from_columns(to_std_cols)
+    to_tower = mat_from_columns(cols)
     from_tower = mat_inv(to_tower)
     # affine matrix: b'_i = b_i ^ b_{i+4} ^ b_{i+5} ^ b_{i+6} ^ b_{i+7}
     aff = [0] * 8
@@ -489,42 +563,45 @@ def synthesize(nu, lam, beta, rng=None, w3: float = 1.5):
         for k in (0, 4, 5, 6, 7):
             aff[i] |= 1 << ((i + k) % 8)
     out_mat = mat_mul(aff, from_tower)
-    S, outs = build_inverse(nu, lam, to_tower, out_mat)
+    S, outs = build_inverse(rep, to_tower, out_mat)
     nodes, order, out_vars = build_netlist(S, outs, rng, w3)
     lut = cover_lut3(nodes, order, out_vars)
     return lut, order, out_vars
 
 
 def search(seeds: int = 0, weights=(1.5, 1.75)):
-    """Try every tower (nu, lam, beta) and triple weight w3; for each, index
+    """Try every basis choice (normal or polynomial at the two upper tower
+    levels), tower (nu, lam, beta) and triple weight w3; for each, index
     tie-breaking plus `seeds` seeded random tie-breakings of the XOR sharing."""
     import random
     table = aes_sbox_table()
     best = None
-    for nu in (2, 3):
-        if not irreducible_quadratic(nu, g4_mul, 4):
-            continue
-        for lam in range(1, 16):
-            if not irreducible_quadratic(lam, lambda a, b: g16_mul(a, b, nu), 16):
+    for nb16, nb256 in itertools.product((False, True), repeat=2):
+        for nu in (2, 3):
+            if not irreducible_quadratic(nu, g4_mul, 4):
                 continue
-            for beta, w3, seed in itertools.product(tower_roots_of_aes_poly(nu, lam), weights, range(-1, seeds)):
-                rng = random.Random(seed) if seed >= 0 else None
-                lut, order, out_vars = synthesize(nu, lam, beta, rng, w3)
-                # Outputs must be distinct LUT nodes (no plain input passthrough).
-                if len(set(out_vars)) != 8 or any(v < 8 for v in out_vars):
+            for lam in range(1, 16):
+                if not irreducible_quadratic(lam, lambda a, b: g16_mul(a, b, nu), 16):
                     continue
-                outs = evaluate(lut, order, out_vars, 0x63, bitsliced_inputs())
-                got = [sum(((outs[b] >> x) & 1) << b for b in range(8)) for x in range(256)]
-                if got != table:
-                    raise AssertionError(f"circuit wrong for nu={nu} lam={lam} beta={beta}")
-                cost = len(lut)
-                if best is None or cost < best[0]:
-                    best = (cost, nu, lam, beta, lut, order, out_vars, seed, w3)
+                for beta, w3, seed in itertools.product(tower_roots_of_aes_poly(nu, lam), weights,
+                                                        range(-1, seeds)):
+                    rng = random.Random(seed) if seed >= 0 else None
+                    lut, order, out_vars = synthesize(nu, lam, beta, rng, w3, nb16, nb256)
+                    # Outputs must be distinct LUT nodes (no plain input passthrough).
+                    if len(set(out_vars)) != 8 or any(v < 8 for v in out_vars):
+                        continue
+                    outs = evaluate(lut, order, out_vars, 0x63, bitsliced_inputs())
+                    got = [sum(((outs[b] >> x) & 1) << b for b in range(8)) for x in range(256)]
+                    if got != table:
+                        raise AssertionError(f"circuit wrong for nu={nu} lam={lam} beta={beta}")
+                    cost = len(lut)
+                    if best is None or cost < best[0]:
+                        best = (cost, nu, lam, beta, lut, order, out_vars, seed, w3, nb16, nb256)
     return best
 
 
 def emit(best, path):
-    cost, nu, lam, beta, lut, order, out_vars, seed, w3 = best
+    cost, nu, lam, beta, lut, order, out_vars, seed, w3, nb16, nb256 = best
     names = {i: f"x[{i}]" for i in range(8)}
     lines = []
     tmp = 0
@@ -563,7 +640,9 @@ def emit(best, path):
         "// sbox_circuit.inc -- generated by gen_sbox_circuit.py; do not edit.",
         "// Bitsliced AES S-box (FIPS-197 Sec. 5.1.1) as a straight-line program of",
         f"// {cost} three-input boolean functions (v_bitop3_b32), derived from the",
-        f"// tower field GF(((2^2)^2)^2) with nu={nu}, lambda={lam}, beta={beta}",
+        f"// tower field GF(((2^2)^2)^2) with nu={nu}, lambda={lam}, beta={beta},",
+        f"// {'normal' if nb16 else 'polynomial'} basis over GF(4), "
+        f"{'normal' if nb256 else 'polynomial'} basis over GF(16)",
         f"// (XOR sharing with triple weight {w3}, tie-break seed {seed}).",
         "// x[b] holds bit b (LSB = 0) of 32 bytes; on return x[b] holds bit b of",
         "// their S-box values.  bitop3(a, b, c, T) must compute the function whose",
