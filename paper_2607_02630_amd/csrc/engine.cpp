@@ -10,7 +10,9 @@
 //      it as one persistent batch kernel -- requests that arrived while other
 //      launches were running join the next one, and launches on different
 //      streams overlap on the device;
-//   3. sleeps when there is nothing queued and nothing in flight.
+//   3. sleeps when there is nothing queued and nothing in flight, after
+//      polling for new work for kIdleSpinNs (a sleeping driver costs the
+//      next request a thread wake-up on its way to the GPU).
 // Request records (pointers, counter parameters, expanded key material) are
 // built on the submitting thread, so the driver only copies them into the
 // launch's descriptor table.
@@ -226,6 +228,9 @@ int launch_batch(aes_engine *e, int s, const std::vector<Req> &batch, std::vecto
     return rc;
 }
 
+// How long an idle driver keeps polling for work before it sleeps.
+constexpr int64_t kIdleSpinNs = 100000;
+
 void drive(aes_engine *e)
 {
     if (hipSetDevice(e->device) != hipSuccess) {
@@ -239,6 +244,7 @@ void drive(aes_engine *e)
     std::vector<aesctr::ShaRecord> hashes;
     int active = 0;
     int64_t busy_since = 0;
+    int64_t idle_since = -1;
     for (;;) {
         bool progressed = false;
         for (int s = 0; s < ns; ++s) {
@@ -276,12 +282,20 @@ void drive(aes_engine *e)
             e->inflight[s].swap(batch);
             progressed = true;
         }
-        if (!progressed) {
-            if (active > 0) {
+        if (progressed) {
+            idle_since = -1;
+        } else if (active > 0) {
+            std::this_thread::yield();
+        } else {
+            if (e->core.closing_and_drained())
+                break;
+            const int64_t now = Core::now_ns();
+            if (idle_since < 0)
+                idle_since = now;
+            if (now - idle_since < kIdleSpinNs) {
                 std::this_thread::yield();
             } else {
-                if (e->core.closing_and_drained())
-                    break;
+                idle_since = -1;
                 e->core.wait_for_work(2000000);
             }
         }
