@@ -141,9 +141,62 @@ constexpr uint32_t row1_dsel(int r)
     return s;
 }
 
+// AES-256's nibble-form round keys in LDS, read back 16 bytes at a time
+// (the same address for every lane).  Held in scalar registers, its 104 words
+// spill to vector-register lanes and come back with a v_readlane each (about
+// 120 per block); the kernel is bound by VALU issue, and LDS is otherwise
+// idle.  AES-128's 72 words stay in scalar registers (about 30 spilled reads
+// per block, which measured cheaper than the LDS reads).
+template <int NR>
+constexpr bool keys_in_lds() { return NR == 14; }
+
+struct VpKeyTable {
+    u32x4 k[13][2];     // [t - 1]: (rki, rkk) of round t; [0]: round 1's constant rows
+    u32x4 kn;           // rkn
+};
+
+// Filled by lane 0 of the workgroup (wave-uniform sources, no per-lane
+// indexing of the argument block).
+template <int NR>
+__device__ __forceinline__ void fill_keys(const VpArgs &a, VpKeyTable &t)
+{
+    if (keys_in_lds<NR>() && threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NR - 1; ++i) {
+            t.k[i][0] = u32x4{a.rki[i][0], a.rki[i][1], a.rki[i][2], a.rki[i][3]};
+            t.k[i][1] = u32x4{a.rkk[i][0], a.rkk[i][1], a.rkk[i][2], a.rkk[i][3]};
+        }
+        t.kn = u32x4{a.rkn[0], a.rkn[1], a.rkn[2], a.rkn[3]};
+    }
+}
+
+// Round t's key rows (i and k nibbles), t = 1..NR-1 (t = 1: round 1's
+// constant rows), and the last round's.
+template <int NR>
+__device__ __forceinline__ void round_keys(const VpArgs &a, const VpKeyTable &kt, int t, u32x4 &ki, u32x4 &kk)
+{
+    if constexpr (keys_in_lds<NR>()) {
+        ki = kt.k[t - 1][0];
+        kk = kt.k[t - 1][1];
+    } else {
+        ki = u32x4{a.rki[t - 1][0], a.rki[t - 1][1], a.rki[t - 1][2], a.rki[t - 1][3]};
+        kk = u32x4{a.rkk[t - 1][0], a.rkk[t - 1][1], a.rkk[t - 1][2], a.rkk[t - 1][3]};
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ u32x4 last_key(const VpArgs &a, const VpKeyTable &kt)
+{
+    if constexpr (keys_in_lds<NR>())
+        return kt.kn;
+    else
+        return u32x4{a.rkn[0], a.rkn[1], a.rkn[2], a.rkn[3]};
+}
+
 // Keystream block of counter value ctr (already ctr0 + j) -> column words.
 template <int NR>
-__device__ __forceinline__ void keystream_vp(const VpArgs &a, uint32_t ctr, uint32_t (&ks)[4])
+__device__ __forceinline__ void keystream_vp(const VpArgs &a, const VpKeyTable &kt, uint32_t ctr,
+                                             uint32_t (&ks)[4])
 {
     // Round 0 of the counter column: ctr xor rk0 in standard bytes (byte r =
     // row r), converted to (i, k) nibbles.
@@ -163,10 +216,12 @@ __device__ __forceinline__ void keystream_vp(const VpArgs &a, uint32_t ctr, uint
         const uint32_t SI = out_of<kVp_si_f, kVp_si_g>(c), SK = out_of<kVp_sk_f, kVp_sk_g>(c);
         const uint32_t DI = out_of<kVp_di_f, kVp_di_g>(c), DK = out_of<kVp_dk_f, kVp_dk_g>(c);
         const uint32_t TI = SI ^ DI, TK = SK ^ DK;
+        u32x4 ki, kk;
+        round_keys<NR>(a, kt, 1, ki, kk);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            I[r] = xor3(vperm(TI, SI, row1_sel(r)), vperm(DI, DI, row1_dsel(r)), a.rki[0][r]);
-            K[r] = xor3(vperm(TK, SK, row1_sel(r)), vperm(DK, DK, row1_dsel(r)), a.rkk[0][r]);
+            I[r] = xor3(vperm(TI, SI, row1_sel(r)), vperm(DI, DI, row1_dsel(r)), ki[r]);
+            K[r] = xor3(vperm(TK, SK, row1_sel(r)), vperm(DK, DK, row1_dsel(r)), kk[r]);
         }
     }
 #pragma unroll
@@ -180,11 +235,13 @@ __device__ __forceinline__ void keystream_vp(const VpArgs &a, uint32_t ctr, uint
             DI[r] = out_of<kVp_di_f, kVp_di_g>(c);
             DK[r] = out_of<kVp_dk_f, kVp_dk_g>(c);
         }
+        u32x4 ki, kk;
+        round_keys<NR>(a, kt, t, ki, kk);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int r1 = (r + 1) & 3, r2 = (r + 2) & 3, r3 = (r + 3) & 3;
-            I[r] = xor3(xor3(DI[r], DI[r1], SI[r1]), xor3(SI[r2], SI[r3], a.rki[t - 1][r]), 0u);
-            K[r] = xor3(xor3(DK[r], DK[r1], SK[r1]), xor3(SK[r2], SK[r3], a.rkk[t - 1][r]), 0u);
+            I[r] = xor3(xor3(DI[r], DI[r1], SI[r1]), xor3(SI[r2], SI[r3], ki[r]), 0u);
+            K[r] = xor3(xor3(DK[r], DK[r1], SK[r1]), xor3(SK[r2], SK[r3], kk[r]), 0u);
         }
     }
     uint32_t row[4];
@@ -193,7 +250,7 @@ __device__ __forceinline__ void keystream_vp(const VpArgs &a, uint32_t ctr, uint
         const Chain c = chain(rotr(I[r], 8 * r), rotr(K[r], 8 * r));
         const Pair f = look<kVp_out_f>(c.io, c.ioc);
         const Pair g = look<kVp_out_g>(c.jo, c.joc);
-        row[r] = xor3(xor3(f.a, f.b, g.a), g.b, a.rkn[r]);
+        row[r] = xor3(xor3(f.a, f.b, g.a), g.b, last_key<NR>(a, kt)[r]);
     }
     // Rows -> columns: ks[c] byte r = row[r] byte c.
     const uint32_t t01l = vperm(row[1], row[0], 0x05010400u);   // r0c0 r1c0 r0c1 r1c1
@@ -211,7 +268,17 @@ __global__ __launch_bounds__(256) void ctr_vperm_kernel(const VpArgs a)
 {
     const uint64_t nfull = a.len >> 4;
     const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    __shared__ VpKeyTable kt;
+    if constexpr (keys_in_lds<NR>()) {
+        fill_keys<NR>(a, kt);
+        __syncthreads();
+    }
     for (uint64_t idx = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < nfull; idx += step) {
+        // The key table never changes, but its reads must stay in their
+        // rounds (hoisted out of the loop they would hold every round key in
+        // registers).  A compiler-only barrier (no instruction).
+        if constexpr (keys_in_lds<NR>())
+            asm volatile("" ::: "memory");
         u32x4 d;
         if constexpr (ALIGNED) {
             d = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(a.in) + idx);
@@ -219,7 +286,7 @@ __global__ __launch_bounds__(256) void ctr_vperm_kernel(const VpArgs a)
             __builtin_memcpy(&d, a.in + 16 * idx, 16);
         }
         uint32_t ks[4];
-        keystream_vp<NR>(a, a.ctr0 + static_cast<uint32_t>(idx), ks);
+        keystream_vp<NR>(a, kt, a.ctr0 + static_cast<uint32_t>(idx), ks);
         const u32x4 v = d ^ u32x4{ks[0], ks[1], ks[2], ks[3]};
         if constexpr (ALIGNED) {
             __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(a.out) + idx);
@@ -231,7 +298,7 @@ __global__ __launch_bounds__(256) void ctr_vperm_kernel(const VpArgs a)
     const uint32_t tail = static_cast<uint32_t>(a.len & 15);
     if (tail != 0 && blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) {
         uint32_t ks[4];
-        keystream_vp<NR>(a, a.ctr0 + static_cast<uint32_t>(nfull), ks);
+        keystream_vp<NR>(a, kt, a.ctr0 + static_cast<uint32_t>(nfull), ks);
         const uint64_t off = 16 * nfull;
         for (uint32_t i = 0; i < tail; ++i)
             a.out[off + i] = a.in[off + i] ^ static_cast<uint8_t>(ks[i >> 2] >> (8 * (i & 3)));
