@@ -303,7 +303,7 @@ def measured_traffic(bits, size, variant):
 VALU_PER_BLOCK_8MIB = {128: 347.0, 256: 467.0}
 # VALU lane operations per block of the kernels without LDS tables: the
 # bitsliced and the vector-permute kernels (rocprofv3 SQ_INSTS_VALU at 256 MiB).
-VALU_PER_BLOCK_BS = {128: 682, 256: 941}
+VALU_PER_BLOCK_BS = {128: 678, 256: 934}
 VALU_PER_BLOCK_VP = {128: 2047, 256: 2905}
 
 

@@ -40,7 +40,8 @@ tie-breakings keeps the smallest circuit.  The result is
 checked on all 256 inputs against the S-box computed from its definition,
 and written as straight-line C++ to sbox_circuit.inc.
 
-Usage: python gen_sbox_circuit.py [--out sbox_circuit.inc]
+Usage: python gen_sbox_circuit.py [--seeds N] [--weights W,W] [--bases all|normal]
+                                  [--out sbox_circuit.inc]
 """
 from __future__ import annotations
 
@@ -569,14 +570,14 @@ def synthesize(nu, lam, beta, rng=None, w3: float = 1.5, nb16: bool = False, nb2
     return lut, order, out_vars
 
 
-def search(seeds: int = 0, weights=(1.5, 1.75)):
+def search(seeds: int = 0, weights=(1.5, 1.75), bases=None):
     """Try every basis choice (normal or polynomial at the two upper tower
     levels), tower (nu, lam, beta) and triple weight w3; for each, index
     tie-breaking plus `seeds` seeded random tie-breakings of the XOR sharing."""
     import random
     table = aes_sbox_table()
     best = None
-    for nb16, nb256 in itertools.product((False, True), repeat=2):
+    for nb16, nb256 in (bases or list(itertools.product((False, True), repeat=2))):
         for nu in (2, 3):
             if not irreducible_quadratic(nu, g4_mul, 4):
                 continue
@@ -600,7 +601,7 @@ def search(seeds: int = 0, weights=(1.5, 1.75)):
     return best
 
 
-def emit(best, path):
+def emit(best, path, options: str = ""):
     cost, nu, lam, beta, lut, order, out_vars, seed, w3, nb16, nb256 = best
     names = {i: f"x[{i}]" for i in range(8)}
     lines = []
@@ -643,7 +644,8 @@ def emit(best, path):
         f"// tower field GF(((2^2)^2)^2) with nu={nu}, lambda={lam}, beta={beta},",
         f"// {'normal' if nb16 else 'polynomial'} basis over GF(4), "
         f"{'normal' if nb256 else 'polynomial'} basis over GF(16)",
-        f"// (XOR sharing with triple weight {w3}, tie-break seed {seed}).",
+        f"// (XOR sharing with triple weight {w3}, tie-break seed {seed}; generator options:",
+        f"// {options or '(defaults)'}).",
         "// x[b] holds bit b (LSB = 0) of 32 bytes; on return x[b] holds bit b of",
         "// their S-box values.  bitop3(a, b, c, T) must compute the function whose",
         "// value for inputs (a, b, c) is bit (a<<2 | b<<1 | c) of T.",
@@ -657,11 +659,16 @@ def emit(best, path):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--seeds", type=int, default=24)
+    ap.add_argument("--weights", default="1.5,1.75", help="triple weights w3 to try, comma-separated")
+    ap.add_argument("--bases", choices=("all", "normal"), default="all",
+                    help="all four basis choices, or normal bases at both upper levels only")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "sbox_circuit.inc"))
     args = ap.parse_args()
-    best = search(args.seeds)
-    cost = emit(best, args.out)
+    weights = tuple(float(w) for w in args.weights.split(","))
+    bases = [(True, True)] if args.bases == "normal" else None
+    best = search(args.seeds, weights, bases)
+    cost = emit(best, args.out, f"--seeds {args.seeds} --weights {args.weights} --bases {args.bases}")
     print(f"S-box circuit: {cost} bitop3 nodes (nu={best[1]} lam={best[2]} beta={best[3]}) -> {args.out}")
 
 
