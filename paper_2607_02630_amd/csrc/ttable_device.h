@@ -95,11 +95,17 @@ __device__ __forceinline__ uint32_t lds_at(const char *lds, uint32_t byte_addr)
 }
 
 // The LDS image is fill_stores(LAYOUT) 16-byte stores: 8192 (128 KiB), or
-// 4096 (64 KiB) for kLayout2x32.  Thread t performs stores w = t + u*WG, each
-// a 4-way broadcast of one table entry (a run of four copies).  The entries
-// are read from the constant table first (fill_read) so the caller can issue
-// its own global loads before the table reads are waited for; fill_write then
-// stores them.
+// 4096 (64 KiB) for kLayout2x32.  Each store is a 4-way broadcast of one
+// table entry (a run of four copies).  The entries are read from the constant
+// table first (fill_read) so the caller can issue its own global loads before
+// the table reads are waited for; fill_write then stores them.
+//  * kLayout4x32, kLayout2x64: thread t performs stores w = t + u*WG, one
+//    value read per store.
+//  * kLayout2x32: two stores per value read, so a value needs one rotate and
+//    one set of register copies for both.  The 16 stores of entry i (8 per
+//    table) come from threads 8i' + 4h + q (i' = i mod WG/8), which write
+//    quads q + 4h and then q + 4(1 - h) of table h's half of the entry: the
+//    8 threads of an entry cover all 32 banks in each store instruction.
 constexpr int kFillStores = 8192;
 
 constexpr int fill_stores(int layout) { return layout == kLayout2x32 ? kFillStores / 2 : kFillStores; }
@@ -107,16 +113,33 @@ constexpr int fill_stores(int layout) { return layout == kLayout2x32 ? kFillStor
 template <int LAYOUT, int WG>
 __device__ __forceinline__ void fill_read(uint32_t (&tv)[kFillStores / WG])
 {
-    // Stores per table entry: 32 (four tables or 64 copies), 16 (kLayout2x32).
-    constexpr int shift = LAYOUT == kLayout2x32 ? 4 : 5;
+    if constexpr (LAYOUT == kLayout2x32) {
 #pragma unroll
-    for (int u = 0; u < fill_stores(LAYOUT) / WG; ++u)
-        tv[u] = c_tables.t0[(threadIdx.x + u * WG) >> shift];
+        for (int u = 0; u < 2048 / WG; ++u)
+            tv[u] = c_tables.t0[(threadIdx.x >> 3) + u * (WG / 8)];
+    } else {
+#pragma unroll
+        for (int u = 0; u < fill_stores(LAYOUT) / WG; ++u)
+            tv[u] = c_tables.t0[(threadIdx.x + u * WG) >> 5];
+    }
 }
 
 template <int LAYOUT, int WG>
 __device__ __forceinline__ void fill_write(uint32_t *lds, const uint32_t (&tv)[kFillStores / WG])
 {
+    if constexpr (LAYOUT == kLayout2x32) {
+        const uint32_t t = threadIdx.x, q = t & 3, h = (t >> 2) & 1;
+        const uint32_t a0 = (t >> 3) * 256 + h * 128 + q * 16 + h * 64, a1 = a0 ^ 64;
+        char *base = reinterpret_cast<char *>(lds);
+#pragma unroll
+        for (int u = 0; u < 2048 / WG; ++u) {
+            const uint32_t val = h ? rotl32(tv[u], 16) : tv[u];
+            const u32x4 v4{val, val, val, val};
+            *reinterpret_cast<u32x4 *>(base + a0 + u * 32 * WG) = v4;
+            *reinterpret_cast<u32x4 *>(base + a1 + u * 32 * WG) = v4;
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < fill_stores(LAYOUT) / WG; ++u) {
         const uint32_t w = threadIdx.x + u * WG;
