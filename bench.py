@@ -300,7 +300,7 @@ def measured_traffic(bits, size, variant):
 # 8 MiB, table fill and per-wave setup included: rocprofv3 SQ_INSTS_VALU x 64
 # / blocks (two-table layout, 512-thread workgroups, two per CU, each wave
 # computing its first chunk's group constants).
-VALU_PER_BLOCK_8MIB = {128: 347.0, 256: 467.0}
+VALU_PER_BLOCK_8MIB = {128: 329.5, 256: 449.5}
 # VALU lane operations per block of the kernels without LDS tables: the
 # bitsliced and the vector-permute kernels (rocprofv3 SQ_INSTS_VALU at 256 MiB).
 VALU_PER_BLOCK_BS = {128: 678, 256: 934}
