@@ -204,7 +204,9 @@ int aes_ctr_crypt_batch(const aes_ctr_desc_t *desc, size_t n, void *stream);
  * sized to the batch, about sixteen per CU within 2-64 KiB; 2 blocks per
  * lane; 1024-thread workgroups, one per CU; a tune cache may override).
  * use_graph: 1 = captured graph, 0 = plain copy + launch; a call without cfg
- * uses the graph; batches of at most 8 requests use neither. */
+ * uses the graph; batches of at most 8 requests use neither: their kernel
+ * has 256-thread workgroups, a wave per tile up to twice `grid` workgroups,
+ * and takes tile_bytes and blocks_per_lane from cfg like the table kernel. */
 typedef struct {
     int32_t tile_bytes;
     int32_t wg_size;

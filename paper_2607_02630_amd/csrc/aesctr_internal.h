@@ -223,7 +223,8 @@ struct SmallBatchArgs {
 };
 static_assert(sizeof(SmallBatchArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
-int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int wg, int bpl, hipStream_t st);
+// grid: workgroups of the argument-path kernel's own size (256 threads).
+int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int bpl, hipStream_t st);
 
 // One request as the host keeps it before staging: its descriptor (key field
 // not yet assigned) and its round keys.

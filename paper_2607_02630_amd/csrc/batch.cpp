@@ -13,6 +13,7 @@
 // part of every upload (0), so no memset node is needed.  The call cannot
 // itself be captured into a caller's graph (its staging would be rewritten
 // by later calls): on a capturing stream it returns AES_EINVAL.
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -188,7 +189,10 @@ namespace {
 constexpr size_t kRecordGrain = 256;
 
 // A batch of at most kSmallBatch requests goes in the kernel's argument block
-// (no staging slot, no upload).  Returns AES_OK, AES_ERANGE or AES_EDEVICE.
+// (no staging slot, no upload).  Its kernel has four waves per workgroup and
+// sizes its own grid: a wave per tile, at most two workgroups per CU of the
+// table kernel's grid (which is at most one per CU), the waves looping over
+// further tiles.  Returns AES_OK, AES_ERANGE or AES_EDEVICE.
 int launch_small(hipStream_t st, const LaunchSpec &spec, uint32_t tile_blocks, int grid, int bpl)
 {
     SmallBatchArgs args{};
@@ -227,7 +231,10 @@ int launch_small(hipStream_t st, const LaunchSpec &spec, uint32_t tile_blocks, i
     args.total_tiles = static_cast<uint32_t>(tiles);
     args.tile_blocks = tile_blocks;
     args.resident = spec.resident;
-    return launch_ctr_batch_small(args, grid, 1024, bpl, st);
+    const uint64_t want = (tiles + 3) / 4;
+    const uint64_t cap = 2 * static_cast<uint64_t>(grid);
+    const int small_grid = static_cast<int>(std::max<uint64_t>(1, std::min(want, cap)));
+    return launch_ctr_batch_small(args, small_grid, bpl, st);
 }
 
 // Takes the context's next staging slot once its last launch has finished.

@@ -19,6 +19,12 @@ namespace {
 
 constexpr int kBatchWG = 1024;
 constexpr int kBatchLayout = kLayout4x32;
+// The argument-path kernel (at most kSmallBatch requests, mostly a tile or
+// two per wave) keeps the single-buffer kernel's small-message shape: 256
+// threads, two tables x 32 copies (half the fill), rounds 1-2 in full (no
+// group-constant chain of scalar loads ahead of the rounds).
+constexpr int kSmallWG = 256;
+constexpr int kSmallLayout = kLayout2x32;
 
 // Request pointers arrive as integers; these types keep their accesses in the
 // global address space (global_load/store rather than flat).
@@ -34,13 +40,20 @@ typedef __attribute__((address_space(4))) const uint32_t c_u32;
 
 // Blocks [b0, b1) of one request.  The loop trip count is the same for every
 // lane (the round-1/2 sharing needs the whole wave), and lane i of each step
-// holds block s0 + 64*b + i.
-template <int NR, int BPL, bool ALIGNED>
-__device__ __forceinline__ void run_tile(const TTable<kBatchLayout> &tt, const CtrArgs &a, uint64_t b0,
+// holds block s0 + 64*b + i.  FULL: rounds 1-2 of every block in full
+// instead of from the wave's group constants.
+template <int NR, int LAYOUT, int BPL, bool ALIGNED, bool FULL>
+__device__ __forceinline__ void run_tile(const TTable<LAYOUT> &tt, const CtrArgs &a, uint64_t b0,
                                          uint64_t b1, uint32_t lane)
 {
     const uint64_t nfull = a.len >> 4;
-    uint32_t krot[1];   // unused by the four-table layout
+    // rotr(rk, 8) of rounds 2..Nr-1 for the two-table fold (the four-table
+    // layout reads none).
+    uint32_t krot[60];
+    if constexpr (LAYOUT != kLayout4x32) {
+#pragma unroll
+        for (int i = 8; i < 4 * NR; ++i) krot[i] = rotr8(a.rk[i]);
+    }
     for (uint64_t s0 = b0; s0 < b1; s0 += 64 * BPL) {
         uint32_t ctr[BPL], ks[BPL][4];
         u32x4 d[BPL];
@@ -60,8 +73,12 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchLayout> &tt, const C
                 }
             }
         }
-        const WaveGroups w = wave_groups<BPL>(a, a.ctr0 + static_cast<uint32_t>(s0));
-        keystream_wave<NR, kBatchLayout, BPL>(tt, a, krot, ctr, w, ks);
+        if constexpr (FULL) {
+            keystream<NR, LAYOUT, BPL>(tt, a, krot, ctr, ks);
+        } else {
+            const WaveGroups w = wave_groups<BPL>(a, a.ctr0 + static_cast<uint32_t>(s0));
+            keystream_wave<NR, LAYOUT, BPL>(tt, a, krot, ctr, w, ks);
+        }
 #pragma unroll
         for (int b = 0; b < BPL; ++b) {
             const uint64_t idx = s0 + 64 * b + lane;
@@ -96,8 +113,8 @@ __device__ __forceinline__ void run_tile(const TTable<kBatchLayout> &tt, const C
 // loads) with round keys rk (wave-uniform, read from the launch's inline keys
 // or from a slot of the resident key table): the request's key material and
 // pointers, then the tile's blocks.
-template <int BPL, class Rec>
-__device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, const Rec &R, const uint32_t (&rk)[60],
+template <int LAYOUT, int BPL, bool FULL, class Rec>
+__device__ __forceinline__ void request_tile(const TTable<LAYOUT> &tt, const Rec &R, const uint32_t (&rk)[60],
                                              uint32_t t, uint32_t tile_blocks, uint32_t lane)
 {
     CtrArgs a;
@@ -119,14 +136,14 @@ __device__ __forceinline__ void request_tile(const TTable<kBatchLayout> &tt, con
     const uint64_t b1 = b0 + tile_blocks < nblocks ? b0 + tile_blocks : nblocks;
     if (R.aligned) {
         if (nr == 10)
-            run_tile<10, BPL, true>(tt, a, b0, b1, lane);
+            run_tile<10, LAYOUT, BPL, true, FULL>(tt, a, b0, b1, lane);
         else
-            run_tile<14, BPL, true>(tt, a, b0, b1, lane);
+            run_tile<14, LAYOUT, BPL, true, FULL>(tt, a, b0, b1, lane);
     } else {
         if (nr == 10)
-            run_tile<10, BPL, false>(tt, a, b0, b1, lane);
+            run_tile<10, LAYOUT, BPL, false, FULL>(tt, a, b0, b1, lane);
         else
-            run_tile<14, BPL, false>(tt, a, b0, b1, lane);
+            run_tile<14, LAYOUT, BPL, false, FULL>(tt, a, b0, b1, lane);
     }
 }
 
@@ -212,7 +229,7 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
 #pragma unroll
             for (int i = 0; i < 60; ++i) rk[i] = p[i];
         }
-        request_tile<BPL>(tt, R, rk, t, tile_blocks, lane);
+        request_tile<kBatchLayout, BPL, false>(tt, R, rk, t, tile_blocks, lane);
         t = waves + __builtin_amdgcn_readfirstlane(claim);
     }
 }
@@ -223,25 +240,27 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_kernel(const uint8_t *__re
 // are assigned statically, wave w taking tiles w, w + W, w + 2W, ... (W
 // waves, numbered as in ctr_batch_kernel), so no work counter is needed.
 template <int BPL>
-__global__ __launch_bounds__(kBatchWG) void ctr_batch_small_kernel(const SmallBatchArgs args)
+__global__ __launch_bounds__(kSmallWG) void ctr_batch_small_kernel(const SmallBatchArgs args)
 {
-    __shared__ uint32_t lds[kLdsWords];
+    __shared__ uint32_t lds[layout_lds_words(kSmallLayout)];
 
-    uint32_t tv[kFillStores / kBatchWG];
-    fill_read<kBatchLayout, kBatchWG>(tv);
+    uint32_t tv[kFillStores / kSmallWG];
+    fill_read<kSmallLayout, kSmallWG>(tv);
     uint32_t *resident = reinterpret_cast<uint32_t *>(args.resident);
     const uint32_t n = args.n;
-    if (blockIdx.x == 0 && threadIdx.x < 64u * kSmallBatch) {
-        const uint32_t i = threadIdx.x >> 6, w = threadIdx.x & 63u;
-        if (i < n && args.r[i].install != kNoInstall && w < 60u)
-            install_key(resident, args.r[i].install, args.r[i].rk, w);
+    if (blockIdx.x == 0) {
+        for (uint32_t j = threadIdx.x; j < 64u * n; j += kSmallWG) {
+            const uint32_t i = j >> 6, w = j & 63u;
+            if (args.r[i].install != kNoInstall && w < 60u)
+                install_key(resident, args.r[i].install, args.r[i].rk, w);
+        }
     }
-    fill_write<kBatchLayout, kBatchWG>(lds, tv);
+    fill_write<kSmallLayout, kSmallWG>(lds, tv);
     __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63;
-    TTable<kBatchLayout> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
-    const uint32_t waves = gridDim.x * (kBatchWG / 64);
+    TTable<kSmallLayout> tt{reinterpret_cast<const char *>(lds), 4 * (lane & 31), 4 * (lane & 31) | 0x10000u};
+    const uint32_t waves = gridDim.x * (kSmallWG / 64);
     for (uint32_t t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
          t < args.total_tiles; t += waves) {
         // Last request whose first tile is <= t (skips empty requests).
@@ -259,7 +278,7 @@ __global__ __launch_bounds__(kBatchWG) void ctr_batch_small_kernel(const SmallBa
 #pragma unroll
             for (int i = 0; i < 60; ++i) rk[i] = R.rk[i];
         }
-        request_tile<BPL>(tt, R, rk, t, args.tile_blocks, lane);
+        request_tile<kSmallLayout, BPL, true>(tt, R, rk, t, args.tile_blocks, lane);
     }
 }
 
@@ -280,14 +299,14 @@ int launch_ctr_batch(const void *dev_table, int grid, int wg, int bpl, hipStream
     return launch_status();
 }
 
-int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int wg, int bpl, hipStream_t st)
+int launch_ctr_batch_small(const SmallBatchArgs &args, int grid, int bpl, hipStream_t st)
 {
-    if (wg != kBatchWG || grid <= 0 || grid > kMaxBatchGrid || args.n > kSmallBatch)
+    if (grid <= 0 || grid > kMaxBatchGrid || args.n > kSmallBatch)
         return AES_EINVAL;
     (void)hipGetLastError();   // not ours: left by earlier calls
     switch (bpl) {
-    case 1: hipLaunchKernelGGL(ctr_batch_small_kernel<1>, dim3(grid), dim3(kBatchWG), 0, st, args); break;
-    case 2: hipLaunchKernelGGL(ctr_batch_small_kernel<2>, dim3(grid), dim3(kBatchWG), 0, st, args); break;
+    case 1: hipLaunchKernelGGL(ctr_batch_small_kernel<1>, dim3(grid), dim3(kSmallWG), 0, st, args); break;
+    case 2: hipLaunchKernelGGL(ctr_batch_small_kernel<2>, dim3(grid), dim3(kSmallWG), 0, st, args); break;
     default: return AES_EINVAL;
     }
     return launch_status();

@@ -81,6 +81,11 @@ __device__ __forceinline__ uint32_t rotl8(uint32_t x)
     return __builtin_amdgcn_alignbit(x, x, 24);
 }
 
+__device__ __forceinline__ uint32_t rotr8(uint32_t x)
+{
+    return __builtin_amdgcn_alignbit(x, x, 8);
+}
+
 // Address of the entry for byte R of v in the table region selected by lb
 // (lb = 4*copy | region << 16): bytes [lb.b0, v.bR, lb.b2, 0].
 template <int R>
